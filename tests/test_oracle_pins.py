@@ -1,0 +1,409 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle.
+
+Each test names the passage of the paper (arXiv 2203.11043) it covers and
+checks it against physics or mathematics that fixes the answer independently:
+Gauss's law, the shell theorem, Newton's third law, exact solutions of the
+forward-Euler recursion, the Einstein relation in measured quantities, the
+two-body and uniform-sphere expansion laws, textbook silicon values and an
+independent Philox implementation (rocRAND, run as a library).
+"""
+import json
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden", "textbook_constants.json")
+HELPER_SRC = os.path.join(ROOT, "tests", "helpers", "rocrand_philox.cpp")
+HELPER_BIN = os.path.join(ROOT, "tests", "helpers", "_build", "rocrand_philox")
+
+
+def golden():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+def fibonacci_sphere(m):
+    k = np.arange(m)
+    zc = 1.0 - (2.0 * k + 1.0) / m
+    r = np.sqrt(1.0 - zc * zc)
+    phi = k * math.pi * (3.0 - math.sqrt(5.0))
+    return np.stack([r * np.cos(phi), r * np.sin(phi), zc])
+
+
+# ---------------------------------------------------------------- Philox (Sec. III.B)
+
+def _rocrand_helper():
+    if os.path.exists(HELPER_BIN):
+        return HELPER_BIN
+    if shutil.which("hipcc") is None:
+        return None
+    os.makedirs(os.path.dirname(HELPER_BIN), exist_ok=True)
+    subprocess.run(["hipcc", "-O1", "-o", HELPER_BIN, HELPER_SRC], check=True)
+    return HELPER_BIN
+
+
+def test_philox_matches_rocrand(orc):
+    """The random diffusion vectors (Sec. III.B, generated in the paper with a
+    library) come from Philox4x32-10; rocRAND's independent implementation of
+    the same published generator must give the same words."""
+    exe = _rocrand_helper()
+    if exe is None:
+        pytest.skip("hipcc not available to build the rocRAND cross-check")
+    g = np.random.default_rng(7)
+    cases = []
+    for _ in range(300):
+        seed = int(g.integers(0, 2**64, dtype=np.uint64))
+        c0, c1 = (int(v) for v in g.integers(0, 2**31, size=2))
+        c2, c3 = (int(v) for v in g.integers(0, 2**32, size=2))
+        cases.append((seed, c0, c1, c2, c3))
+    cases += [(0, 0, 0, 0, 0), (1, 0, 0, 0, 0), (2**64 - 1, 5, 0, 2**32 - 1, 2**32 - 1)]
+    inp = "".join(f"{s} {a} {b} {c} {d}\n" for s, a, b, c, d in cases)
+    out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout
+    ref = [list(map(int, line.split())) for line in out.strip().splitlines()]
+    assert len(ref) == len(cases)
+    for (seed, c0, c1, c2, c3), want in zip(cases, ref):
+        got = orc.philox4x32_10([c0, c1, c2, c3], [seed & 0xFFFFFFFF, seed >> 32]).tolist()
+        assert got == want, (seed, c0, c1, c2, c3)
+
+
+def test_normals_are_standard_gaussian(orc):
+    """Sec. II.B: each coordinate of the diffusion step is normal with mean 0;
+    the Box-Muller draws must be N(0,1), uncorrelated across the 3 axes."""
+    from scipy import stats
+    n = 40000
+    g = np.array([orc.normals(1, j, 17, 0) for j in range(n)])
+    for k in range(3):
+        col = g[:, k]
+        assert abs(col.mean()) < 5.0 / math.sqrt(n)
+        assert abs(col.var() - 1.0) < 5.0 * math.sqrt(2.0 / n)
+        assert stats.kstest(col, "norm").pvalue > 1e-4
+    c = np.corrcoef(g.T)
+    assert np.max(np.abs(c - np.eye(3))) < 5.0 / math.sqrt(n)
+
+
+def test_normals_depend_on_every_counter_word(orc):
+    base = orc.normals(3, 10, 20, 0)
+    for args in [(4, 10, 20, 0), (3, 11, 20, 0), (3, 10, 21, 0), (3, 10, 20, 1),
+                 (3 + (1 << 32), 10, 20, 0)]:
+        assert not np.array_equal(base, orc.normals(*args))
+    assert np.array_equal(base, orc.normals(3, 10, 20, 0))
+
+
+# ---------------------------------------------------------------- Eq. (2) mobility
+
+def test_mobility_textbook_values(orc):
+    """Eq. (2) at 300 K reproduces the textbook low-field hole mobility and
+    saturation velocity of silicon; its high-field limit mu*E follows the
+    Jacoboni et al. saturation-velocity law at every temperature."""
+    gd = golden()
+    si = gd["silicon_holes_300K"]
+    mu300 = orc.mobility(0.0, 300.0)
+    assert si["mobility_cm2_per_Vs_min"] < mu300 < si["mobility_cm2_per_Vs_max"]
+    vs300 = orc.mobility(1e9, 300.0) * 1e9
+    assert si["vsat_cm_per_s_min"] < vs300 < si["vsat_cm_per_s_max"]
+    law = gd["silicon_holes_vsat_law"]
+    for T in (100.0, 140.0, 200.0, 300.0):
+        vs = orc.mobility(1e9, T) * 1e9
+        want = law["prefactor_cm_per_s"] * T ** law["exponent"]
+        assert abs(vs / want - 1.0) < 5e-3
+
+
+def test_mobility_shape(orc):
+    """mu falls and mu*E rises monotonically with E; E -> 0 gives the
+    low-field (constant-model) value; holes are slower when the lattice is
+    hotter (Sec. II.A)."""
+    E = np.geomspace(1e-3, 1e7, 400)
+    mu = np.array([orc.mobility(e, 140.0) for e in E])
+    assert np.all(np.diff(mu) < 0)
+    assert np.all(np.diff(mu * E) > 0)
+    assert abs(orc.mobility(0.0, 140.0) / orc.mobility(0.0, 140.0, 1) - 1.0) < 1e-15
+    assert abs(mu[0] / orc.mobility(0.0, 140.0, 1) - 1.0) < 1e-6
+    assert orc.mobility(100.0, 140.0) > orc.mobility(100.0, 300.0)
+
+
+def test_constants_match_codata(orc):
+    """K of Eq. (6) and k_B T / q of Eq. (4) against scipy's CODATA tables."""
+    from scipy import constants as C
+    K_want = C.e / (4.0 * math.pi * C.epsilon_0 * 11.7) * 1e10  # V um^2 / cm
+    assert abs(orc.coulomb_constant(11.7) / K_want - 1.0) < 1e-8
+    assert abs(orc.thermal_voltage(140.0) / (C.k * 140.0 / C.e) - 1.0) < 1e-8
+
+
+# ---------------------------------------------------------------- Eq. (6) field
+
+def test_field_obeys_gauss_law(orc):
+    """The flux of the field of Eq. (6) through a sphere enclosing all charges
+    is 4 pi K N (Gauss's law): checks the prefactor, the sign and the 1/r^2
+    power of the sum, independently of how it is written."""
+    g = np.random.default_rng(1)
+    N, R, M = 60, 20.0, 40000
+    c = np.array([480.0, 480.0, 300.0])
+    src = c[:, None] + g.uniform(-0.6, 0.6, size=(3, N))
+    nrm = fibonacci_sphere(M)
+    tgt = c[:, None] + R * nrm
+    E = orc.field(tgt, src, softening_um=1e-3)
+    flux = np.sum(E * nrm) * 4.0 * math.pi * R * R / M
+    want = 4.0 * math.pi * orc.coulomb_constant(11.7) * N
+    assert abs(flux / want - 1.0) < 1e-5
+
+
+def test_field_shell_theorem(orc):
+    """Charge spread evenly over a sphere: no field inside, the field of a
+    point charge outside."""
+    N, R = 6000, 10.0
+    c = np.array([100.0, 200.0, 300.0])
+    src = c[:, None] + R * fibonacci_sphere(N)
+    K = orc.coulomb_constant(11.7)
+    scale = K * N / R**2
+    g = np.random.default_rng(2)
+    inside = c[:, None] + g.uniform(-4.0, 4.0, size=(3, 40))
+    Ein = orc.field(inside, src)
+    assert np.max(np.linalg.norm(Ein, axis=0)) < 1e-3 * scale
+    dirs = g.normal(size=(3, 40))
+    dirs /= np.linalg.norm(dirs, axis=0)
+    r_out = 30.0
+    Eout = orc.field(c[:, None] + r_out * dirs, src)
+    want = K * N / r_out**2 * dirs
+    assert np.max(np.linalg.norm(Eout - want, axis=0)) < 1e-4 * K * N / r_out**2
+
+
+def test_field_pairwise_forces_cancel(orc):
+    """r_ij = -r_ji, so the fields of Eq. (6) summed over all carriers vanish
+    (Newton's third law)."""
+    g = np.random.default_rng(3)
+    pts = g.normal(0.0, 1.0, size=(3, 2000)) + np.array([[480.0], [480.0], [300.0]])
+    E = orc.field(pts)
+    tot = np.abs(E.sum(axis=1))
+    assert np.all(tot < 1e-13 * np.abs(E).sum(axis=1))
+
+
+def test_field_softened_point_charge(orc):
+    """One source: the field vanishes at the source itself (the self term of
+    Eq. (6)), is radial, decays as K/r^2 far away, and peaks at r = eps/sqrt(2)
+    (the Plummer-softened kernel's maximum)."""
+    K = orc.coulomb_constant(11.7)
+    eps = 1e-3
+    src = np.array([[5.0], [6.0], [7.0]])
+    assert np.all(orc.field(src, src, softening_um=eps) == 0.0)
+    r = np.geomspace(1e-5, 1.0, 4001)
+    tgt = src + np.outer([0.0, 1.0, 0.0], r)
+    E = orc.field(tgt, src, softening_um=eps)
+    assert np.all(np.abs(E[0]) == 0.0) and np.all(np.abs(E[2]) == 0.0)
+    assert np.all(E[1] > 0.0)
+    assert abs(E[1][-1] * r[-1] ** 2 / K - 1.0) < 2e-6
+    peak = r[np.argmax(E[1])]
+    assert abs(peak / (eps / math.sqrt(2.0)) - 1.0) < 5e-3
+
+
+def test_field_matches_extended_precision(orc):
+    """Brute force at 50 digits (mpmath) on a tiny input bounds the oracle's
+    rounding error relative to the sum of term magnitudes."""
+    import mpmath
+    mpmath.mp.dps = 50
+    g = np.random.default_rng(4)
+    pts = g.normal(0.0, 0.3, size=(3, 24)) + np.array([[10.0], [20.0], [300.0]])
+    E, A = orc.field(pts, with_magnitude=True)
+    K = mpmath.mpf(orc.coulomb_constant(11.7))
+    e2 = mpmath.mpf(1e-3) ** 2
+    for j in range(pts.shape[1]):
+        acc = [mpmath.mpf(0)] * 3
+        for i in range(pts.shape[1]):
+            d = [mpmath.mpf(pts[k, j]) - mpmath.mpf(pts[k, i]) for k in range(3)]
+            q = d[0] ** 2 + d[1] ** 2 + d[2] ** 2 + e2
+            w = q ** mpmath.mpf(-1.5)
+            for k in range(3):
+                acc[k] += d[k] * w
+        for k in range(3):
+            assert abs(float(K * acc[k]) - E[k, j]) <= 1e-14 * A[j]
+
+
+def test_field_invariances(orc):
+    """Translating every point, or permuting the sources, leaves the field
+    unchanged up to rounding; the magnitude sum bounds the field."""
+    g = np.random.default_rng(5)
+    pts = g.normal(0.0, 1.0, size=(3, 500)) + 300.0
+    E, A = orc.field(pts, with_magnitude=True)
+    E2 = orc.field(pts + np.array([[3.25], [-7.5], [1.0]]))
+    assert np.max(np.abs(E2 - E)) < 1e-9 * np.max(A)
+    perm = g.permutation(500)
+    E3 = orc.field(pts, pts[:, perm])
+    assert np.max(np.abs(E3 - E)) < 1e-12 * np.max(A)
+    assert np.all(np.linalg.norm(E, axis=0) <= A * (1 + 1e-12))
+
+
+# ---------------------------------------------------------------- the time step
+
+def dev(orc, **kw):
+    d = orc.Device()
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d
+
+
+def test_drift_time_exact_euler_constant_mobility(orc):
+    """Drift only (Sec. II.A) with constant mobility: forward Euler in the
+    linear field of Eq. (1) has the closed-form iterate
+    z_k = z* + (1 + c)^k (z0 - z*), z* = a2/a1, c = mu0 a1 dt, so the step of
+    arrival at z = 0 is known exactly."""
+    d = dev(orc, coulomb=0, diffusion=0, mobility_model=1)
+    mu0 = 1.31e8 * 140.0 ** -2.2            # Eq. (2) at E = 0
+    dt = 10e-12
+    for z0 in (300.0, 50.0, 650.0):
+        st = orc.State(d, [480.0], [480.0], [z0])
+        done, na = st.run(10.0, 100000)
+        c = mu0 * d.a1 * dt * 1e4
+        zs = d.a2 / d.a1
+        k = math.ceil(math.log(zs / (zs - z0)) / math.log1p(c))
+        assert na == 0 and done == k and st.cstep[0] == k
+        t_exact = math.log(zs / (zs - z0)) / (mu0 * d.a1 * 1e4)
+        # Euler lags the exact flow by about k c / 2 steps, plus the ceiling
+        assert abs(done - t_exact / dt) < 1.0 + 0.5 * k * c
+        assert st.x[0] == 480.0 and st.y[0] == 480.0
+
+
+def test_drift_time_field_dependent_mobility(orc):
+    """Same with Eq. (2): the number of Euler steps agrees with the transit
+    time t = int_0^z0 dz / (mu(E) E) from adaptive quadrature to 2 steps."""
+    from scipy.integrate import quad
+    d = dev(orc, coulomb=0, diffusion=0)
+
+    def mu(E, T=140.0):
+        b = 0.46 * T ** 0.17
+        return 1.31e8 * T ** -2.2 / (1.0 + (E / (1.24 * T ** 1.68)) ** b) ** (1.0 / b)
+
+    for z0 in (300.0, 650.0):
+        t, _ = quad(lambda z: 1.0 / (mu(d.a2 - d.a1 * z) * (d.a2 - d.a1 * z) * 1e4),
+                    0.0, z0, epsabs=0, epsrel=1e-13)
+        st = orc.State(d, [1.0], [1.0], [z0])
+        done, na = st.run(10.0, 100000)
+        assert na == 0
+        assert abs(done - t / 10e-12) <= 2.0
+
+
+def test_einstein_relation_measured(orc):
+    """Uniform field, no Coulomb: the measured spread rate and drift rate obey
+    D / v = k_B T / (q E) (Eqs. (3), (4) with v = mu E), whatever mu is."""
+    from scipy import constants as C
+    d = dev(orc, coulomb=0, a1=0.0, a2=2200.0, seed=11)
+    n, steps = 20000, 200
+    st = orc.State(d, np.zeros(n), np.zeros(n), np.full(n, 600.0))
+    st.run(10.0, steps)
+    assert st.n_active == n
+    var = np.mean([st.x.var(), st.y.var(), st.z.var()])
+    drift = 600.0 - st.z.mean()
+    ratio = var / (2.0 * drift)                       # = D / v, in um
+    want = C.k * 140.0 / C.e / 2200.0 * 1e4           # k_B T / (q E), V/(V/cm) -> um
+    assert abs(ratio / want - 1.0) < 0.02
+    st.run(10.0, steps)                                # spread grows linearly in time
+    var2 = np.mean([st.x.var(), st.y.var(), st.z.var()])
+    assert abs(var2 / var - 2.0) < 0.04
+
+
+def test_lateral_spread_linear_field(orc):
+    """Linear field, no Coulomb: D/v = kT/(qE) and dz/E(z) integrate to
+    sigma_xy^2 = (2 kT / (q a1)) ln(a2 / (a2 - a1 z0)), independent of mu."""
+    from scipy import constants as C
+    d = dev(orc, coulomb=0, seed=5)
+    n, z0 = 20000, 300.0
+    st = orc.State(d, np.full(n, 480.0), np.full(n, 480.0), np.full(n, z0))
+    st.run(10.0, 100000)
+    assert st.n_active == 0
+    var = 0.5 * (st.x.var() + st.y.var())
+    want = 2.0 * C.k * 140.0 / C.e / d.a1 * 1e4 * math.log(d.a2 / (d.a2 - d.a1 * z0))
+    assert abs(var / want - 1.0) < 0.04
+
+
+def test_two_body_mirror_and_expansion(orc):
+    """Two holes, Coulomb only, constant mobility: the pair stays an exact
+    mirror image and separates as d^3 = d0^3 + 6 mu0 K t (Eq. (6), eps << d)."""
+    d = dev(orc, coulomb=1, diffusion=0, mobility_model=1, a1=0.0, a2=0.0)
+    st = orc.State(d, [-0.5, 0.5], [0.0, 0.0], [300.0, 300.0])
+    st.run(10.0, 1000)
+    assert st.x[0] == -st.x[1]
+    assert st.y[0] == 0.0 and st.y[1] == 0.0 and st.z[0] == 300.0
+    mu0 = 1.31e8 * 140.0 ** -2.2
+    K = 1.602176634e-19 / (4 * math.pi * 8.8541878128e-12 * 11.7) * 1e10
+    want = (1.0 + 6.0 * mu0 * K * 1e4 * 1000 * 10e-12) ** (1.0 / 3.0)
+    assert abs((st.x[1] - st.x[0]) / want - 1.0) < 3e-4
+
+
+def test_uniform_sphere_expands_homologously(orc):
+    """A uniformly charged ball expands self-similarly under Eq. (6) with
+    constant mobility: R^3 = R0^3 + 3 mu0 K N t, so <r^2> scales by (R/R0)^2."""
+    g = np.random.default_rng(6)
+    N, R0 = 2000, 2.0
+    u = g.normal(size=(3, N))
+    u /= np.linalg.norm(u, axis=0)
+    r = R0 * g.uniform(size=N) ** (1.0 / 3.0)
+    c = np.array([[0.0], [0.0], [300.0]])
+    p = c + u * r
+    d = dev(orc, coulomb=1, diffusion=0, mobility_model=1, a1=0.0, a2=0.0)
+    st = orc.State(d, p[0], p[1], p[2])
+    r2_0 = np.mean(np.sum((p - c) ** 2, axis=0))
+    st.run(10.0, 200)
+    q = np.stack([st.x, st.y, st.z]) - c
+    r2 = np.mean(np.sum(q ** 2, axis=0))
+    mu0 = 1.31e8 * 140.0 ** -2.2
+    K = 1.602176634e-19 / (4 * math.pi * 8.8541878128e-12 * 11.7) * 1e10
+    R3 = R0**3 + 3.0 * mu0 * K * 1e4 * N * 200 * 10e-12
+    assert abs(r2 / r2_0 / (R3 ** (2 / 3) / R0**2) - 1.0) < 0.01
+
+
+def test_load_reflects_and_collects(orc):
+    d = dev(orc)
+    st = orc.State(d, [0, 0, 0, 0], [0, 0, 0, 0], [680.0, 0.0, -1.0, 10.0])
+    assert st.z[0] == 670.0
+    assert st.cstep.tolist() == [-1, 0, 0, -1]
+    assert st.n_active == 2
+
+
+def test_run_is_resumable(orc):
+    """run(a) then run(b) equals run(a + b) bit for bit: the random draws are
+    keyed on the global step, not on the call."""
+    from paper_2203_11043_amd import workloads as W
+    w = W.single_cloud(300, seed=2, depth_um=40.0)
+    d = dev(orc)
+    a = orc.State(d, w.x, w.y, w.z)
+    a.run(10.0, 50)
+    a.run(10.0, 90)
+    b = orc.State(d, w.x, w.y, w.z)
+    b.run(10.0, 140)
+    assert np.array_equal(a.x, b.x) and np.array_equal(a.z, b.z)
+    assert np.array_equal(a.cstep, b.cstep)
+    assert a.step == b.step
+
+
+def test_full_run_conserves_charge(orc):
+    """Every hole of a 1000-hole cloud ends in exactly one pixel: the image
+    sum plus holes outside plus holes still travelling equals N."""
+    from paper_2203_11043_amd import workloads as W
+    w = W.x_ray_cloud(seed=1)
+    st = orc.State(dev(orc), w.x, w.y, w.z)
+    done, na = st.run(w.dt_ps, 20000)
+    counts, out = st.image(0.0, 0.0, w.pitch_um, w.nx, w.ny)
+    assert na == 0 and out == 0
+    assert int(counts.sum()) + out + na == w.n
+    assert done >= 912                    # the drift time alone from 300 um
+    assert st.cstep.max() == done
+
+
+def test_image_bins_by_hand(orc):
+    """Half-open pixels [k p, (k+1) p) from the grid origin (Sec. V.A)."""
+    x = [0.0, 15.0, 14.999999, 59.999, 60.0, -1e-12, float("nan"), 30.0, 7.0]
+    y = [0.0, 0.0, 59.9999, 0.0, 0.0, 5.0, 1.0, 30.0, 7.0]
+    cs = [0, 3, 9, 1, 1, 1, 2, -1, 5]
+    counts, out = orc.image(x, y, cs, 0.0, 0.0, 15.0, 4, 4)
+    want = np.zeros((4, 4), dtype=np.uint32)
+    want[0, 0] = 2      # (0,0) and (7,7)
+    want[0, 1] = 1      # (15,0)
+    want[3, 0] = 1      # (14.999999, 59.9999)
+    want[0, 3] = 1      # (59.999, 0)
+    assert np.array_equal(counts, want)
+    assert out == 3     # x = 60, x < 0, NaN; the active carrier is not binned
+    c2, o2 = orc.image([100.0, 101.0], [100.0, 100.0], [0, 0], 95.0, 90.0, 5.0, 3, 3)
+    assert c2[2, 1] == 2 and o2 == 0
