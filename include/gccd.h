@@ -1,0 +1,168 @@
+/*
+ * gccd.h -- C ABI of the MI355X (gfx950) charge-transport hot path.
+ *
+ * Implements the time step of N. E. Avalos and M. Sofo Haro, "G-CoReCCD: a
+ * GPU-based simulator of the charge transport in fully-depleted CCDs"
+ * (arXiv 2203.11043): holes created in the bulk of a thick, fully depleted
+ * CCD drift in the linear depletion field (Sec. II.A, Eq. (1)) at the
+ * field-dependent mobility (Eq. (2)), diffuse (Sec. II.B, Eqs. (3)-(4)) and
+ * repel each other through the softened all-pairs Coulomb field (Sec. III.B,
+ * Eq. (6)) until they reach the potential well at the front surface, where
+ * they are binned into pixels (Sec. V.A).
+ *
+ * Conventions
+ *   - Units: lengths in micrometres, z measured from the collection plane
+ *     (z = 0 at the front surface, +z into the bulk); fields in V/cm;
+ *     mobility in cm^2/(V s); the time step in picoseconds.
+ *   - Every function returns GCCD_OK (0) or a negative GCCD_E_* status and
+ *     never throws.  gccd_strerror names a status; gccd_last_error gives the
+ *     detail of the last failure on a context.
+ *   - Array arguments are device pointers (HIP global memory) owned by the
+ *     caller, read or written only during the call, in stream order on the
+ *     context's stream.  The context owns its internal buffers.
+ *   - Calls are asynchronous on the context's stream unless a description
+ *     says it synchronises.  A context is not thread safe; different
+ *     contexts are independent.
+ *   - Carrier state lives in device memory as structure-of-arrays FP64
+ *     positions plus an int32 collection step per carrier.
+ */
+#ifndef GCCD_H
+#define GCCD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GCCD_ABI_VERSION 1u
+
+enum {
+    GCCD_OK = 0,
+    GCCD_E_INVALID = -1,    /* an argument is out of range, NULL or non-finite  */
+    GCCD_E_STATE = -2,      /* call out of order (e.g. run before load)         */
+    GCCD_E_DEVICE = -3,     /* a HIP call failed; see gccd_last_error           */
+    GCCD_E_NOMEM = -4,      /* device allocation failed                         */
+    GCCD_E_NONFINITE = -5   /* a position became non-finite during a run        */
+};
+
+typedef struct gccd_ctx gccd_ctx;   /* opaque; owned by the library */
+
+/* Device and physics settings.  The user inputs listed in Sec. III.B of the
+ * paper (thickness, a1, a2 of Eq. (1), depth of the potential well, the
+ * Coulomb switch) plus the temperature of Eqs. (2) and (4), the permittivity
+ * and softening length of Eq. (6) and the random-number seed. */
+typedef struct {
+    uint32_t abi_version;      /* must equal GCCD_ABI_VERSION                         */
+    uint32_t reserved0;        /* must be 0                                           */
+    double thickness_um;       /* bulk thickness, > 0; z beyond it is mirrored back   */
+    double a1_Vcm_per_um;      /* Eq. (1) slope: E_z(z) = a1 z - a2                   */
+    double a2_Vcm;             /* Eq. (1) offset                                      */
+    double well_z_um;          /* a hole with z <= well_z is collected; < thickness   */
+    double temperature_K;      /* T of Eqs. (2) and (4), > 0                          */
+    double eps_r;              /* relative permittivity in K = q/(4 pi eps0 eps_r), >0*/
+    double softening_um;       /* epsilon of Eq. (6), > 0                             */
+    int32_t coulomb;           /* 1: include Eq. (6); 0: drift and diffusion only     */
+    int32_t diffusion;         /* 1: add the Brownian step of Sec. II.B               */
+    int32_t mobility_model;    /* 0: Eq. (2); 1: constant low-field value of Eq. (2)  */
+    int32_t collected_are_sources; /* 1: collected holes keep repelling (default)    */
+    uint64_t seed;             /* Philox4x32-10 key (low word, high word)             */
+    uint32_t event;            /* third word of every Philox counter                  */
+    uint32_t reserved1;        /* must be 0                                           */
+} gccd_params;
+
+/* Counters kept by a context since its last gccd_load. */
+typedef struct {
+    int64_t step;              /* global step index of the next step                 */
+    int64_t n_carriers;        /* N loaded                                            */
+    int64_t n_active;          /* carriers still travelling                           */
+    uint64_t carrier_steps;    /* sum over steps of the active carriers moved         */
+    uint64_t pair_interactions;/* sum over steps of targets x sources of Eq. (6)      */
+    double field_ms;           /* device time in the Eq. (6) kernel (timing on only)  */
+    int64_t field_launches;    /* launches of that kernel while timing was on        */
+    int32_t targets_per_thread;/* launch shape of the last Eq. (6) launch            */
+    int32_t source_chunks;
+} gccd_stats_t;
+
+/* Creates a context bound to the current HIP device and to hip_stream (a
+ * hipStream_t; NULL means the null stream).  Validates every field of *p
+ * before touching the device: GCCD_E_INVALID for a wrong abi_version,
+ * non-finite values, thickness, temperature, eps_r or softening <= 0,
+ * well_z >= thickness, or switches outside {0, 1}.  GCCD_E_DEVICE when no
+ * GPU is usable.  On success *out owns no carrier buffers yet. */
+int gccd_init(const gccd_params* p, void* hip_stream, gccd_ctx** out);
+
+/* Loads n carriers (Sec. III.B: the step loop starts from hole positions
+ * that are already resident in device memory): x, y, z are device arrays of n FP64
+ * positions in um, copied into the context.  A z beyond the back surface is
+ * mirrored back; a z at or below the well is collected at step 0.  Resets the
+ * step counter and every statistic.  GCCD_E_INVALID for n <= 0, n > 2^31-1
+ * or a NULL pointer; GCCD_E_NOMEM if buffers cannot be allocated.  Non-finite
+ * input positions make the next gccd_run return GCCD_E_NONFINITE. */
+int gccd_load(gccd_ctx* c, int64_t n, const double* x, const double* y, const double* z);
+
+/* Advances the simulation (Sec. III.B, Fig. 2) by up to max_steps time steps
+ * of dt_ps picoseconds.  Each step computes, for every travelling hole, the
+ * static field of Eq. (1), the Coulomb field of Eq. (6) from the positions at
+ * the start of the step, the mobility of Eq. (2) at the magnitude of their
+ * sum, the drift mu E dt and the diffusion step of Eqs. (3)-(4) (Philox4x32-10
+ * counter (carrier, step, event, 0), Box-Muller), then moves it in FP64 and
+ * collects it when z <= well_z.  Stops early when no hole travels.  Runs are
+ * cumulative: run(a) then run(b) equals run(a+b) bit for bit.  Synchronises
+ * the stream every few steps and at return.  *steps_done (may be NULL) gets
+ * the steps that had travelling holes, *n_active (may be NULL) the holes still
+ * travelling; running out of steps is not an error.  GCCD_E_INVALID for
+ * dt_ps <= 0 or max_steps < 0, GCCD_E_STATE before gccd_load,
+ * GCCD_E_NONFINITE if a position became NaN or infinite (the context then
+ * needs a new gccd_load before the next run, field or image). */
+int gccd_run(gccd_ctx* c, double dt_ps, int64_t max_steps, int64_t* steps_done,
+             int64_t* n_active);
+
+/* Image of the collected holes (Sec. V.A: a 2D histogram of the final
+ * positions, bin size equal to the pixel width).  Pixel (ix, iy) covers
+ * [x0 + ix p, x0 + (ix+1) p) x [y0 + iy p, y0 + (iy+1) p), with the index
+ * floor((x - x0) / p) computed in IEEE FP64.  counts is a device array of
+ * ny*nx uint32, row-major (iy major), overwritten; *n_outside is a device
+ * uint64 that receives the collected holes outside the grid.  Holes still
+ * travelling are not counted.  GCCD_E_INVALID for pitch <= 0, nx or ny <= 0,
+ * nx*ny > 2^31, non-finite origin, NULL pointers; GCCD_E_STATE before load. */
+int gccd_image(gccd_ctx* c, double x0_um, double y0_um, double pitch_um, int32_t nx,
+               int32_t ny, uint32_t* counts, uint64_t* n_outside);
+
+/* The Coulomb field of Eq. (6), in V/cm, at every loaded carrier from the
+ * current sources (all carriers, or only travelling ones when
+ * collected_are_sources is 0), computed by the same kernel and launch shape
+ * as gccd_run.  ex, ey, ez are device arrays of n FP64 values.
+ * GCCD_E_STATE before load, GCCD_E_INVALID for NULL pointers. */
+int gccd_field(gccd_ctx* c, double* ex, double* ey, double* ez);
+
+/* Copies the current FP64 positions and collection steps (-1 while a hole
+ * travels, else the step count at which it arrived; 0 for holes loaded at or
+ * below the well) into device arrays of n elements.  Any pointer may be NULL
+ * to skip it.  GCCD_E_STATE before load. */
+int gccd_positions(gccd_ctx* c, double* x, double* y, double* z, int32_t* collect_step);
+
+/* Fills *out with the counters above; synchronises the stream. */
+int gccd_stats(gccd_ctx* c, gccd_stats_t* out);
+
+/* Fixes the launch shape of the Eq. (6) kernel: targets per thread (1, 2 or
+ * 4) and the number of source chunks each target's sum is split into (1-32).
+ * 0 for either means "choose automatically" (the default).  Results do not
+ * depend on the targets per thread; the split changes only the FP32
+ * summation order.  GCCD_E_INVALID outside those ranges. */
+int gccd_set_launch(gccd_ctx* c, int32_t targets_per_thread, int32_t source_chunks);
+
+/* on = 1 times every Eq. (6) launch with HIP events on the context's stream
+ * (reported by gccd_stats); on = 0 stops timing. */
+int gccd_set_timing(gccd_ctx* c, int32_t on);
+
+const char* gccd_strerror(int status);
+const char* gccd_last_error(const gccd_ctx* c);
+
+/* Frees the context and its device buffers.  NULL is ignored. */
+void gccd_destroy(gccd_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
