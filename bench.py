@@ -24,6 +24,26 @@ if ROOT not in sys.path:
 
 PEAK_FP32_TFLOPS = 157.3       # MI355X published FP32 vector peak
 FLOP_PER_PAIR = 20             # N-body convention for one softened interaction
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "field_tiles_cloud_n100000_traffic.json")
+
+
+def measured_traffic(n: int, tpt: int, chunks: int):
+    """HBM bytes per Eq. (6) launch from the FETCH_SIZE / WRITE_SIZE counter
+    runs recorded under profiles/, scaled by the copy-kernel calibration;
+    None when the kernel source or the launch shape differs from the one the
+    counters were taken on."""
+    import hashlib
+    try:
+        with open(TRAFFIC_RECORD) as f:
+            rec = json.load(f)
+        with open(os.path.join(ROOT, rec["kernel_source"]), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, KeyError, ValueError):
+        return None
+    if (sha != rec.get("kernel_source_sha256") or n != 100000
+            or tpt != rec.get("targets_per_thread") or chunks != rec.get("source_chunks")):
+        return None
+    return rec["hbm_bytes_per_launch"]
 
 
 def cpu_baseline(w, max_seconds: float = 12.0) -> dict:
@@ -53,7 +73,7 @@ def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=100000)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--tpt", type=int, default=0, help="targets per thread (0 = auto)")
@@ -148,7 +168,8 @@ def main() -> int:
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": kern_tflops / PEAK_FP32_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(w.n, s1["targets_per_thread"], s1["source_chunks"]),
+            "traffic_unit": "bytes per launch (HBM, counter-measured)",
             "avg_launch_ms": kern_s / launches * 1e3,
             "pairs_per_launch": pairs / launches,
             "flop_per_pair": FLOP_PER_PAIR,

@@ -121,11 +121,15 @@ def test_field_full_size_sampled(g, W, orc, n):
 
 
 def test_field_muon_track_sampled(g, W, orc):
+    """A straight track through the whole thickness: some holes start beyond
+    the back surface and are mirrored at load, on both sides."""
     w = W.muon_track(seed=1)
     p, d = dev_params(g, W)
     E, st = gpu_field(g, p, w.x, w.y, w.z)
+    o = orc.State(oracle_device(orc, d), w.x, w.y, w.z)     # load-time mirror
+    assert np.any(w.z > d["thickness_um"])
     idx = np.random.default_rng(9).choice(w.n, 256, replace=False)
-    Eo, A = orc.field([w.x[idx], w.y[idx], w.z[idx]], [w.x, w.y, w.z], with_magnitude=True)
+    Eo, A = orc.field([o.x[idx], o.y[idx], o.z[idx]], [o.x, o.y, o.z], with_magnitude=True)
     ea, er = field_errors(E[:, idx], Eo, A)
     report(f"track n={w.n} (256 sampled)", ea, er)
     assert ea <= FIELD_TOL
@@ -300,7 +304,7 @@ def test_load_boundary_handling(g, W, orc):
     o = orc.State(oracle_device(orc, d), x, x, z)
     assert np.array_equal(pos.cpu().numpy()[2], o.z)
     assert np.array_equal(cs.cpu().numpy(), o.cstep)
-    assert st["n_active"] == o.n_active == 3
+    assert st["n_active"] == o.n_active == 4     # 670 (mirrored), 10, 675, 1e-9
 
 
 def test_everything_collected_at_load(g, W):
