@@ -96,7 +96,7 @@ int gccd_init(const gccd_params* p, void* hip_stream, gccd_ctx** out);
  * that are already resident in device memory): x, y, z are device arrays of n FP64
  * positions in um, copied into the context.  A z beyond the back surface is
  * mirrored back; a z at or below the well is collected at step 0.  Resets the
- * step counter and every statistic.  GCCD_E_INVALID for n <= 0, n > 2^31-1
+ * step counter and every statistic.  GCCD_E_INVALID for n <= 0, n > 2^27
  * or a NULL pointer; GCCD_E_NOMEM if buffers cannot be allocated.  Non-finite
  * input positions make the next gccd_run return GCCD_E_NONFINITE. */
 int gccd_load(gccd_ctx* c, int64_t n, const double* x, const double* y, const double* z);
@@ -146,7 +146,7 @@ int gccd_positions(gccd_ctx* c, double* x, double* y, double* z, int32_t* collec
 int gccd_stats(gccd_ctx* c, gccd_stats_t* out);
 
 /* Fixes the launch shape of the Eq. (6) kernel: targets per thread (1, 2 or
- * 4) and the number of source chunks each target's sum is split into (1-32).
+ * 4) and the number of source chunks each target's sum is split into (1-64).
  * 0 for either means "choose automatically" (the default).  Results do not
  * depend on the targets per thread; the split changes only the FP32
  * summation order.  GCCD_E_INVALID outside those ranges. */

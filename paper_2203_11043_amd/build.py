@@ -13,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libgccd.so")
 SOURCES = [os.path.join(HERE, "csrc", "gccd_api.hip"),
+           os.path.join(HERE, "csrc", "gccd_sort.hip"),
            os.path.join(HERE, "csrc", "gccd_kernels.hip")]
 ARCH = os.environ.get("GCCD_OFFLOAD_ARCH", "gfx950")
 

@@ -22,6 +22,7 @@ constexpr double kEps0 = 8.8541878128e-12;
 constexpr double kPi = 3.14159265358979323846;
 
 constexpr int kPoll = 32;  // steps between host reads of the active count
+constexpr int64_t kMaxCarriers = 1ll << 27;  // carrier index fits the low key bits
 
 // Small device block of counters: [0..2] active counts (ring of three, by step
 // mod 3), [3] non-finite flag, [4] step after the last step with travelling
@@ -44,7 +45,22 @@ struct gccd_ctx {
     double* y = nullptr;
     double* z = nullptr;
     int32_t* cstep = nullptr;
-    int32_t* list[2] = {nullptr, nullptr};
+    // key lists: keys[cur] holds this step's travelling holes (sorted when
+    // Coulomb is on), keys[cur ^ 1] receives the next step's, keys[2] is
+    // scratch for gccd_field
+    uint64_t* keys[3] = {nullptr, nullptr, nullptr};
+    int cur = 0;
+    uint32_t idx_bits = 1;
+    void* sort_tmp = nullptr;
+    size_t sort_tmp_bytes = 0;
+    // lists hold all n carriers (Coulomb on, collected holes are sources) or
+    // only the travelling ones
+    bool full_list = false;
+    double* tile_box = nullptr;  // [6][tile_stride] source-tile bounding boxes
+    uint32_t tile_stride = 0;
+    // positions gathered into list-slot order: set 0 for the run's list (the
+    // Eq. (6) sources, and its targets), set 1 for gccd_field's targets
+    double* ps[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
     float* part = nullptr;
     uint32_t* meta = nullptr;
     uint32_t* host_meta = nullptr;  // pinned
@@ -108,12 +124,22 @@ void free_buffers(gccd_ctx* c) {
     (void)hipFree(c->y);
     (void)hipFree(c->z);
     (void)hipFree(c->cstep);
-    (void)hipFree(c->list[0]);
-    (void)hipFree(c->list[1]);
+    for (int i = 0; i < 3; ++i) (void)hipFree(c->keys[i]);
+    (void)hipFree(c->sort_tmp);
+    (void)hipFree(c->tile_box);
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 3; ++b) {
+            (void)hipFree(c->ps[a][b]);
+            c->ps[a][b] = nullptr;
+        }
     (void)hipFree(c->part);
     c->x = c->y = c->z = nullptr;
     c->cstep = nullptr;
-    c->list[0] = c->list[1] = nullptr;
+    c->keys[0] = c->keys[1] = c->keys[2] = nullptr;
+    c->sort_tmp = nullptr;
+    c->sort_tmp_bytes = 0;
+    c->tile_box = nullptr;
+    c->tile_stride = 0;
     c->part = nullptr;
     c->cap = 0;
 }
@@ -125,13 +151,17 @@ void free_buffers(gccd_ctx* c) {
 // loaded carrier count only -- never from how many are still travelling --
 // and every step of a load, and gccd_field, sums in the same order.
 void choose_shape(const gccd_ctx* c, uint32_t nt, uint32_t ns, int* tpt, int* chunks) {
-    int t = c->tpt_fixed;
-    if (t == 0) t = (nt >= 65536u) ? 2 : 1;
+    // One target per lane: the smallest workgroup box, hence the fewest
+    // close pairs taking the exact-difference branch, and 62 VGPRs (eight
+    // waves per SIMD).  Measured faster than two or four per lane.
+    int t = c->tpt_fixed ? c->tpt_fixed : 1;
     int s = c->chunks_fixed;
     if (s == 0) {
         const uint64_t per_block = (uint64_t)kFieldThreads * t;
         const uint64_t tblocks = (nt + per_block - 1) / per_block;
-        const uint64_t want = (uint64_t)c->n_cu * 8;  // workgroups to fill the chip
+        // about 48 waves per SIMD in total (6 rounds of 8 resident), which
+        // evens out workgroups whose boxes see more close pairs
+        const uint64_t want = (uint64_t)c->n_cu * 48;
         uint64_t k = tblocks ? (want + tblocks - 1) / tblocks : 1;
         const uint64_t by_tiles = ns / (4u * kTile);  // keep >= 4 tiles per chunk
         if (k > by_tiles) k = by_tiles;
@@ -243,31 +273,63 @@ void gccd_destroy(gccd_ctx* c) {
 
 int gccd_load(gccd_ctx* c, int64_t n, const double* x, const double* y, const double* z) {
     if (!c) return GCCD_E_INVALID;
-    if (n <= 0 || n > 2147483647LL || !x || !y || !z)
+    if (n <= 0 || n > kMaxCarriers || !x || !y || !z)
         return fail(c, GCCD_E_INVALID, "gccd_load: n out of range or NULL pointer");
+    uint32_t bits = 1;
+    while ((1ll << bits) < n) ++bits;
     if (n > c->cap) {
         GCCD_HIP(c, hipStreamSynchronize(c->stream));
         free_buffers(c);
         const size_t d = (size_t)n * sizeof(double);
         const size_t i = (size_t)n * sizeof(int32_t);
-        if (hipMalloc(&c->x, d) != hipSuccess || hipMalloc(&c->y, d) != hipSuccess ||
-            hipMalloc(&c->z, d) != hipSuccess || hipMalloc(&c->cstep, i) != hipSuccess ||
-            hipMalloc(&c->list[0], i) != hipSuccess || hipMalloc(&c->list[1], i) != hipSuccess ||
-            hipMalloc(&c->part, (size_t)kMaxChunks * 3 * (size_t)n * sizeof(float)) !=
-                hipSuccess) {
+        const size_t k = (size_t)n * sizeof(uint64_t);
+        bool ok = hipMalloc(&c->x, d) == hipSuccess && hipMalloc(&c->y, d) == hipSuccess &&
+                  hipMalloc(&c->z, d) == hipSuccess && hipMalloc(&c->cstep, i) == hipSuccess &&
+                  hipMalloc(&c->keys[0], k) == hipSuccess &&
+                  hipMalloc(&c->keys[1], k) == hipSuccess &&
+                  hipMalloc(&c->keys[2], k) == hipSuccess &&
+                  hipMalloc(&c->tile_box, 6 * sizeof(double) * (size_t)((n + kTile - 1) / kTile)) ==
+                      hipSuccess &&
+                  hipMalloc(&c->ps[0][0], d) == hipSuccess && hipMalloc(&c->ps[0][1], d) == hipSuccess &&
+                  hipMalloc(&c->ps[0][2], d) == hipSuccess && hipMalloc(&c->ps[1][0], d) == hipSuccess &&
+                  hipMalloc(&c->ps[1][1], d) == hipSuccess && hipMalloc(&c->ps[1][2], d) == hipSuccess &&
+                  hipMalloc(&c->part, (size_t)kMaxChunks * 3 * (size_t)n * sizeof(float)) ==
+                      hipSuccess;
+        if (!ok) {
             free_buffers(c);
             c->loaded = false;
             return fail(c, GCCD_E_NOMEM, "gccd_load: device allocation failed");
         }
         c->cap = n;
+        c->tile_stride = (uint32_t)((n + kTile - 1) / kTile);
     }
+    size_t need = 0;
+    GCCD_HIP(c, sort_keys_storage((uint32_t)n, kMortonBits + 1u + bits, &need));
+    if (need > c->sort_tmp_bytes) {
+        (void)hipFree(c->sort_tmp);
+        c->sort_tmp = nullptr;
+        c->sort_tmp_bytes = 0;
+        if (hipMalloc(&c->sort_tmp, need) != hipSuccess) {
+            free_buffers(c);
+            c->loaded = false;
+            return fail(c, GCCD_E_NOMEM, "gccd_load: sort storage allocation failed");
+        }
+        c->sort_tmp_bytes = need;
+    }
+    c->idx_bits = bits;
     const size_t bytes = (size_t)n * sizeof(double);
     GCCD_HIP(c, hipMemcpyAsync(c->x, x, bytes, hipMemcpyDeviceToDevice, c->stream));
     GCCD_HIP(c, hipMemcpyAsync(c->y, y, bytes, hipMemcpyDeviceToDevice, c->stream));
     GCCD_HIP(c, hipMemcpyAsync(c->z, z, bytes, hipMemcpyDeviceToDevice, c->stream));
     GCCD_HIP(c, launch_fill_u32(c->meta, kMetaWords, 0u, c->stream));
-    GCCD_HIP(c, launch_load(c->z, c->cstep, c->list[0], c->meta + 0, (uint32_t)n,
-                            c->p.thickness_um, c->p.well_z_um, c->stream));
+    c->full_list = c->p.coulomb && c->p.collected_are_sources;
+    if (!c->full_list) GCCD_HIP(c, launch_fill_u64(c->keys[1], (uint64_t)n, kNoKey, c->stream));
+    GCCD_HIP(c, launch_load(c->z, c->cstep, c->keys[1], c->meta + 0, c->x, c->y, (uint32_t)n,
+                            bits, c->full_list ? 1 : 0, c->p.thickness_um, c->p.well_z_um,
+                            c->stream));
+    GCCD_HIP(c, sort_keys(c->sort_tmp, c->sort_tmp_bytes, c->keys[1], c->keys[0], (uint32_t)n,
+                          kMortonBits + 1u + bits, c->stream));
+    c->cur = 0;
     GCCD_HIP(c, hipMemcpyAsync(c->host_meta, c->meta, kMetaWords * sizeof(uint32_t),
                                hipMemcpyDeviceToHost, c->stream));
     GCCD_HIP(c, hipStreamSynchronize(c->stream));
@@ -321,6 +383,7 @@ int gccd_run(gccd_ctx* c, double dt_ps, int64_t max_steps, int64_t* steps_done,
     sa.mobility_model = c->p.mobility_model;
     sa.src_all = c->p.collected_are_sources;
     sa.n_all = n;
+    sa.idx_bits = c->idx_bits;
     sa.K = c->K;
     sa.a1 = c->p.a1_Vcm_per_um;
     sa.a2 = c->p.a2_Vcm;
@@ -338,40 +401,43 @@ int gccd_run(gccd_ctx* c, double dt_ps, int64_t max_steps, int64_t* steps_done,
     sa.stats = reinterpret_cast<unsigned long long*>(c->meta + 8);
     sa.misc = reinterpret_cast<int32_t*>(c->meta + 3);
 
+    const uint64_t idx_mask = (1ull << c->idx_bits) - 1ull;
     FieldArgs fa{};
-    fa.x = c->x;
-    fa.y = c->y;
-    fa.z = c->z;
+    fa.tx = fa.sx = c->ps[0][0];
+    fa.ty = fa.sy = c->ps[0][1];
+    fa.tz = fa.sz = c->ps[0][2];
+    fa.tile_box = c->tile_box;
+    fa.tile_stride = c->tile_stride;
     fa.eps2 = (float)(c->p.softening_um * c->p.softening_um);
     fa.part = c->part;
     fa.pstride = n;
+    int tpt, chunks;
+    choose_shape(c, n, n, &tpt, &chunks);
+    const uint32_t end_bit = kMortonBits + 1u + c->idx_bits;
+    sa.full_list = c->full_list ? 1 : 0;
 
     int64_t k = 0;
     while (k < max_steps && bound > 0) {
         const int64_t chunk_steps = (max_steps - k < kPoll) ? (max_steps - k) : kPoll;
         for (int64_t i = 0; i < chunk_steps; ++i) {
             const uint32_t s = (uint32_t)(step0 + k + i);
-            int32_t* lin = c->list[s & 1u];
-            int32_t* lout = c->list[(s + 1u) & 1u];
+            uint64_t* kin = c->keys[c->cur];
+            uint64_t* kout = c->keys[c->cur ^ 1];
             uint32_t* cin = c->meta + (s % 3u);
             if (c->p.coulomb) {
-                fa.tlist = lin;
+                // targets: the travelling holes, first in the list; sources:
+                // the whole list (full) or the same travelling holes; both
+                // read from the slot-ordered copy gathered here
                 fa.tcount = cin;
                 fa.nt = bound;
-                if (c->p.collected_are_sources) {
-                    fa.slist = nullptr;
-                    fa.scount = nullptr;
-                    fa.ns = n;
-                } else {
-                    fa.slist = lin;
-                    fa.scount = cin;
-                    fa.ns = bound;
-                }
-                int tpt, chunks;
-                choose_shape(c, n, n, &tpt, &chunks);
+                fa.scount = c->full_list ? nullptr : cin;
+                fa.ns = c->full_list ? n : bound;
                 fa.nchunk = chunks;
                 c->last_tpt = tpt;
                 c->last_chunks = chunks;
+                GCCD_HIP(c, launch_gather(kin, fa.scount, fa.ns, fa.ns, idx_mask, n, c->x, c->y,
+                                          c->z, c->ps[0][0], c->ps[0][1], c->ps[0][2],
+                                          c->tile_box, c->tile_stride, c->stream));
                 hipEvent_t* evp = nullptr;
                 int r = record_field_start(c, &evp);
                 if (r != GCCD_OK) return r;
@@ -381,13 +447,22 @@ int gccd_run(gccd_ctx* c, double dt_ps, int64_t max_steps, int64_t* steps_done,
             } else {
                 sa.nchunk = 0;
             }
-            sa.list_in = lin;
+            if (!c->full_list) GCCD_HIP(c, launch_fill_u64(kout, bound, kNoKey, c->stream));
+            sa.keys_in = kin;
             sa.cnt_in = cin;
-            sa.list_out = lout;
+            sa.keys_out = kout;
             sa.cnt_out = c->meta + ((s + 1u) % 3u);
             sa.cnt_clear = c->meta + ((s + 2u) % 3u);
             sa.step = s;
             GCCD_HIP(c, launch_step(sa, bound, c->stream));
+            if (c->p.coulomb) {
+                // next step's list in spatial order, travelling holes first
+                // (the unused tail of a travelling-only list holds kNoKey)
+                GCCD_HIP(c, sort_keys(c->sort_tmp, c->sort_tmp_bytes, kout, kin,
+                                      c->full_list ? n : bound, end_bit, c->stream));
+            } else {
+                c->cur ^= 1;
+            }
         }
         k += chunk_steps;
         GCCD_HIP(c, hipMemcpyAsync(c->host_meta, c->meta, kMetaWords * sizeof(uint32_t),
@@ -425,32 +500,69 @@ int gccd_field(gccd_ctx* c, double* ex, double* ey, double* ez) {
     if (!ex || !ey || !ez) return fail(c, GCCD_E_INVALID, "gccd_field: NULL pointer");
     const uint32_t n = (uint32_t)c->n;
     const uint32_t s = (uint32_t)c->step;
+    const uint32_t end_bit = kMortonBits + 1u + c->idx_bits;
+    const uint64_t idx_mask = (1ull << c->idx_bits) - 1ull;
     FieldArgs fa{};
-    fa.x = c->x;
-    fa.y = c->y;
-    fa.z = c->z;
-    fa.tlist = nullptr;
-    fa.tcount = nullptr;
-    fa.nt = n;
-    if (c->p.collected_are_sources) {
-        fa.slist = nullptr;
-        fa.scount = nullptr;
-        fa.ns = n;
-    } else {
-        fa.slist = c->list[s & 1u];
-        fa.scount = c->meta + (s % 3u);
-        fa.ns = (uint32_t)c->n_active;
-    }
+    fa.tile_box = c->tile_box;
+    fa.tile_stride = c->tile_stride;
     fa.eps2 = (float)(c->p.softening_um * c->p.softening_um);
     fa.part = c->part;
     fa.pstride = n;
+    fa.nt = n;
+    fa.tcount = nullptr;
+    fa.sx = c->ps[0][0];
+    fa.sy = c->ps[0][1];
+    fa.sz = c->ps[0][2];
+    const uint64_t* tkeys = nullptr;
+    if (c->full_list || c->p.collected_are_sources) {
+        // every carrier is both a target and a source: the run's list when it
+        // holds all of them, else all keys sorted into the unused list
+        const uint64_t* all = c->keys[c->cur];
+        if (!c->full_list) {
+            uint64_t* tk = c->keys[c->cur ^ 1];
+            GCCD_HIP(c, launch_keys_all(c->x, c->y, c->z, n, c->idx_bits, c->keys[2], c->stream));
+            GCCD_HIP(c, sort_keys(c->sort_tmp, c->sort_tmp_bytes, c->keys[2], tk, n, end_bit,
+                                  c->stream));
+            all = tk;
+        }
+        GCCD_HIP(c, launch_gather(all, nullptr, n, n, idx_mask, n, c->x, c->y, c->z, c->ps[0][0],
+                                  c->ps[0][1], c->ps[0][2], c->tile_box, c->tile_stride,
+                                  c->stream));
+        fa.tx = c->ps[0][0];
+        fa.ty = c->ps[0][1];
+        fa.tz = c->ps[0][2];
+        fa.scount = nullptr;
+        fa.ns = n;
+        tkeys = all;
+    } else {
+        // sources: the travelling holes (the run's list); targets: every
+        // carrier, sorted into the unused list
+        uint32_t* cnt = c->meta + (s % 3u);
+        const uint32_t na = (uint32_t)c->n_active;
+        GCCD_HIP(c, launch_gather(c->keys[c->cur], cnt, na, na, idx_mask, n, c->x, c->y, c->z,
+                                  c->ps[0][0], c->ps[0][1], c->ps[0][2], c->tile_box,
+                                  c->tile_stride, c->stream));
+        uint64_t* tk = c->keys[c->cur ^ 1];
+        GCCD_HIP(c, launch_keys_all(c->x, c->y, c->z, n, c->idx_bits, c->keys[2], c->stream));
+        GCCD_HIP(c, sort_keys(c->sort_tmp, c->sort_tmp_bytes, c->keys[2], tk, n, end_bit,
+                              c->stream));
+        GCCD_HIP(c, launch_gather(tk, nullptr, n, n, idx_mask, n, c->x, c->y, c->z, c->ps[1][0],
+                                  c->ps[1][1], c->ps[1][2], nullptr, 0, c->stream));
+        fa.tx = c->ps[1][0];
+        fa.ty = c->ps[1][1];
+        fa.tz = c->ps[1][2];
+        fa.scount = cnt;
+        fa.ns = na;
+        tkeys = tk;
+    }
     int tpt, chunks;
     choose_shape(c, n, n, &tpt, &chunks);
     fa.nchunk = chunks;
     c->last_tpt = tpt;
     c->last_chunks = chunks;
     GCCD_HIP(c, launch_field(fa, tpt, n, c->stream));
-    GCCD_HIP(c, launch_field_finish(c->part, n, chunks, n, c->K, ex, ey, ez, c->stream));
+    GCCD_HIP(c, launch_field_finish(c->part, n, chunks, tkeys, idx_mask, n, c->K, ex, ey, ez,
+                                    c->stream));
     return GCCD_OK;
 }
 

@@ -11,51 +11,173 @@
 namespace gccd {
 
 // ---------------------------------------------------------------------------
+// Spatial keys.  A hole's 0.25 um cell (12 bits per axis, wrapping every
+// 1024 um) is interleaved bit by bit into a 36-bit Morton code, placed above
+// the carrier index; one more bit above the code marks a collected hole, so a
+// sorted list holds the travelling holes first, each part in spatial order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t cell12(double v) {
+    if (!isfinite(v)) return 0u;
+    return (uint32_t)(int64_t)floor(v * kCellPerUm) & 0xFFFu;
+}
+
+__device__ __forceinline__ uint64_t morton36(uint32_t cx, uint32_t cy, uint32_t cz) {
+    uint64_t m = 0;
+#pragma unroll
+    for (int b = 0; b < 12; ++b) {
+        m |= (uint64_t)((cx >> b) & 1u) << (3 * b);
+        m |= (uint64_t)((cy >> b) & 1u) << (3 * b + 1);
+        m |= (uint64_t)((cz >> b) & 1u) << (3 * b + 2);
+    }
+    return m;
+}
+
+__device__ __forceinline__ uint64_t spatial_key(double x, double y, double z, uint32_t j,
+                                                uint32_t idx_bits, bool collected) {
+    const uint64_t flag = collected ? (1ull << (kMortonBits + idx_bits)) : 0ull;
+    return flag | (morton36(cell12(x), cell12(y), cell12(z)) << idx_bits) | (uint64_t)j;
+}
+
+// ---------------------------------------------------------------------------
 // Eq. (6):  E_j = K sum_i r_ij / (|r_ij|^2 + eps^2)^{3/2},  r_ij = r_j - r_i.
 //
-// One workgroup owns kFieldThreads*TPT target slots and one chunk of the
+// One workgroup owns kFieldThreads*TPT consecutive target slots of the
+// spatially sorted list (a compact region of the cloud) and one chunk of the
 // sources.  Sources are staged through LDS in tiles of kTile (double
 // buffered: the next tile's global loads are in flight while the current one
-// is consumed); every lane of every wave reads the same LDS word, so the
+// is consumed); every lane of every wave reads the same LDS words, so the
 // reads are bank-conflict-free broadcasts.  Each lane keeps TPT targets in
 // registers for independent dependency chains.
 //
-// Precision: positions are FP64.  Each coordinate is carried as an FP32 pair
-// hi = fl32(x), lo = fl32(x - hi), so x - x' = (hi - hi') + (lo - lo'); the
-// hi difference is exact whenever the two points are close, and the pair
-// difference keeps about 48 bits without FP64 arithmetic in the loop.  The
-// rest of the pair math is FP32 with the hardware reciprocal square root.
+// Precision.  The workgroup takes the centre o of its targets' bounding box
+// (half-diagonal rho) as origin and holds every coordinate, targets and
+// staged sources alike, as the FP32 pair hi = fl32(x - o), lo = fl32(x - o -
+// hi).  A pair difference d is first formed from the hi parts alone; its
+// error is at most 2u (rho + |d|), and since the Jacobian of d/|d|^3 has norm
+// 2/|d|^3 the term's relative error is at most 4u (1 + rho/|d|).  Pairs
+// closer than rho/4 -- rare, and found with one compare per pair, or ruled
+// out for a whole source tile by its bounding box -- are recomputed with the
+// lo parts added, which makes their difference accurate to about u |d|.
+// Every term therefore carries at most 20u (1.2e-6) relative error from the
+// coordinates, plus about 8u from r^2, the hardware reciprocal square root
+// (cubed for r^-3) and the products, so each carrier's field is within about
+// 2e-6 of the sum of its term magnitudes plus the FP32 summation error.
 // Each tile's contributions are summed separately and then added to the
-// running sum (blocked summation), which keeps the FP32 rounding growth at
-// O(sqrt(tile) + sqrt(sources/tile)) instead of O(sqrt(sources)).
+// running sum (blocked summation).
 // ---------------------------------------------------------------------------
-template <int TPT>
-__device__ __forceinline__ void pair_terms(float shx, float shy, float shz, float slx,
-                                           float sly, float slz, const float (&thx)[TPT],
+template <int TPT, bool CHECK>
+__device__ __forceinline__ void pair_terms(const float* __restrict__ lxp,
+                                           const float* __restrict__ lyp,
+                                           const float* __restrict__ lzp, uint32_t k, float shx,
+                                           float shy, float shz, const float (&thx)[TPT],
                                            const float (&thy)[TPT], const float (&thz)[TPT],
                                            const float (&tlx)[TPT], const float (&tly)[TPT],
-                                           const float (&tlz)[TPT], float eps2,
+                                           const float (&tlz)[TPT], float eps2, float rc2,
                                            float (&ax)[TPT], float (&ay)[TPT],
                                            float (&az)[TPT]) {
+    float dx[TPT], dy[TPT], dz[TPT], r2[TPT];
+    bool near = false;
 #pragma unroll
     for (int t = 0; t < TPT; ++t) {
-        float dx = (thx[t] - shx) + (tlx[t] - slx);
-        float dy = (thy[t] - shy) + (tly[t] - sly);
-        float dz = (thz[t] - shz) + (tlz[t] - slz);
-        float r2 = __builtin_fmaf(dx, dx, eps2);
-        r2 = __builtin_fmaf(dy, dy, r2);
-        r2 = __builtin_fmaf(dz, dz, r2);
-        float inv = __builtin_amdgcn_rsqf(r2);
-        float w = inv * inv * inv;
-        ax[t] = __builtin_fmaf(dx, w, ax[t]);
-        ay[t] = __builtin_fmaf(dy, w, ay[t]);
-        az[t] = __builtin_fmaf(dz, w, az[t]);
+        dx[t] = thx[t] - shx;
+        dy[t] = thy[t] - shy;
+        dz[t] = thz[t] - shz;
+        r2[t] = __builtin_fmaf(dx[t], dx[t], eps2);
+        r2[t] = __builtin_fmaf(dy[t], dy[t], r2[t]);
+        r2[t] = __builtin_fmaf(dz[t], dz[t], r2[t]);
+        if (CHECK) near |= r2[t] < rc2;
     }
+    if (CHECK && __builtin_expect(__ballot(near) != 0ull, 0)) {
+        // wave-uniform branch, taken only when some lane of the wave has a
+        // close pair: add the lo parts to the differences of those pairs
+        const float slx = lxp[k], sly = lyp[k], slz = lzp[k];
+#pragma unroll
+        for (int t = 0; t < TPT; ++t) {
+            if (r2[t] < rc2) {
+                dx[t] += tlx[t] - slx;
+                dy[t] += tly[t] - sly;
+                dz[t] += tlz[t] - slz;
+                r2[t] = __builtin_fmaf(dx[t], dx[t], eps2);
+                r2[t] = __builtin_fmaf(dy[t], dy[t], r2[t]);
+                r2[t] = __builtin_fmaf(dz[t], dz[t], r2[t]);
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < TPT; ++t) {
+        // r^-3 as rsq^3: one transcendental and two multiplies measured
+        // faster on gfx950 than rsq * rcp (two transcendentals, one multiply)
+        const float inv = __builtin_amdgcn_rsqf(r2[t]);
+        const float w = inv * inv * inv;
+        ax[t] = __builtin_fmaf(dx[t], w, ax[t]);
+        ay[t] = __builtin_fmaf(dy[t], w, ay[t]);
+        az[t] = __builtin_fmaf(dz[t], w, az[t]);
+    }
+}
+
+// All pairs of one staged tile (cnt sources) with the lane's TPT targets.
+template <int TPT, bool CHECK>
+__device__ __forceinline__ void tile_terms(const float* __restrict__ hxp,
+                                           const float* __restrict__ hyp,
+                                           const float* __restrict__ hzp,
+                                           const float* __restrict__ lxp,
+                                           const float* __restrict__ lyp,
+                                           const float* __restrict__ lzp, uint32_t cnt,
+                                           const float (&thx)[TPT], const float (&thy)[TPT],
+                                           const float (&thz)[TPT], const float (&tlx)[TPT],
+                                           const float (&tly)[TPT], const float (&tlz)[TPT],
+                                           float eps2, float rc2, float (&bx)[TPT],
+                                           float (&by)[TPT], float (&bz)[TPT]) {
+    uint32_t k = 0;
+    for (; k + 4 <= cnt; k += 4) {
+        const float4 hx4 = *reinterpret_cast<const float4*>(hxp + k);
+        const float4 hy4 = *reinterpret_cast<const float4*>(hyp + k);
+        const float4 hz4 = *reinterpret_cast<const float4*>(hzp + k);
+        pair_terms<TPT, CHECK>(lxp, lyp, lzp, k + 0, hx4.x, hy4.x, hz4.x, thx, thy, thz, tlx, tly,
+                               tlz, eps2, rc2, bx, by, bz);
+        pair_terms<TPT, CHECK>(lxp, lyp, lzp, k + 1, hx4.y, hy4.y, hz4.y, thx, thy, thz, tlx, tly,
+                               tlz, eps2, rc2, bx, by, bz);
+        pair_terms<TPT, CHECK>(lxp, lyp, lzp, k + 2, hx4.z, hy4.z, hz4.z, thx, thy, thz, tlx, tly,
+                               tlz, eps2, rc2, bx, by, bz);
+        pair_terms<TPT, CHECK>(lxp, lyp, lzp, k + 3, hx4.w, hy4.w, hz4.w, thx, thy, thz, tlx, tly,
+                               tlz, eps2, rc2, bx, by, bz);
+    }
+    for (; k < cnt; ++k) {
+        pair_terms<TPT, CHECK>(lxp, lyp, lzp, k, hxp[k], hyp[k], hzp[k], thx, thy, thz, tlx, tly,
+                               tlz, eps2, rc2, bx, by, bz);
+    }
+}
+
+// A value every lane of the wave holds identically, moved to scalar
+// registers (the compiler cannot prove uniformity after a shuffle reduction).
+__device__ __forceinline__ double uniform(double v) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__device__ __forceinline__ float uniform(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = fmin(v, __shfl_xor(v, m));
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m));
+    return v;
 }
 
 template <int TPT>
 __global__ __launch_bounds__(kFieldThreads) void field_tiles(FieldArgs a) {
     __shared__ __align__(16) float sh[2][6][kTile];
+    __shared__ double box[6][kFieldThreads / 64];
+    __shared__ double tbox[2][6];  // bounding box of the staged source tile
 
     const uint32_t nt = a.tcount ? *a.tcount : a.nt;
     const uint32_t ns = a.scount ? *a.scount : a.ns;
@@ -63,64 +185,127 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles(FieldArgs a) {
     const uint32_t tbase = (blockIdx.x / (uint32_t)a.nchunk) * (uint32_t)(kFieldThreads * TPT);
     if (tbase >= nt) return;  // the whole workgroup leaves before any barrier
 
-    const uint32_t s_begin = (uint32_t)(((uint64_t)ns * (uint64_t)chunk) / (uint64_t)a.nchunk);
-    const uint32_t s_end = (uint32_t)(((uint64_t)ns * (uint64_t)(chunk + 1)) / (uint64_t)a.nchunk);
+    // Chunk c takes the source tiles c, c + S, c + 2S, ... of the T tiles of
+    // kTile slots.  Each tile is a compact region (the list is spatially
+    // sorted) whose bounding box is precomputed; dealing them round-robin
+    // gives every chunk a sample of the whole cloud, so the close pairs --
+    // the costlier ones -- spread evenly over the workgroups.
+    const uint32_t ntiles = (ns + kTile - 1) / kTile;
+    const uint32_t step_t = (uint32_t)a.nchunk;
     const int tid = threadIdx.x;
+
+    // targets and their bounding box
+    double px[TPT], py[TPT], pz[TPT];
+    double lo_x = INFINITY, lo_y = INFINITY, lo_z = INFINITY;
+    double hi_x = -INFINITY, hi_y = -INFINITY, hi_z = -INFINITY;
+#pragma unroll
+    for (int t = 0; t < TPT; ++t) {
+        const uint32_t slot = tbase + (uint32_t)(t * kFieldThreads + tid);
+        px[t] = py[t] = pz[t] = 0.0;
+        if (slot < nt) {
+            px[t] = a.tx[slot];
+            py[t] = a.ty[slot];
+            pz[t] = a.tz[slot];
+            lo_x = fmin(lo_x, px[t]);
+            lo_y = fmin(lo_y, py[t]);
+            lo_z = fmin(lo_z, pz[t]);
+            hi_x = fmax(hi_x, px[t]);
+            hi_y = fmax(hi_y, py[t]);
+            hi_z = fmax(hi_z, pz[t]);
+        }
+    }
+    {
+        const int wave = tid >> 6, lane = tid & 63;
+        lo_x = wave_min(lo_x);
+        lo_y = wave_min(lo_y);
+        lo_z = wave_min(lo_z);
+        hi_x = wave_max(hi_x);
+        hi_y = wave_max(hi_y);
+        hi_z = wave_max(hi_z);
+        if (lane == 0) {
+            box[0][wave] = lo_x;
+            box[1][wave] = lo_y;
+            box[2][wave] = lo_z;
+            box[3][wave] = hi_x;
+            box[4][wave] = hi_y;
+            box[5][wave] = hi_z;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < kFieldThreads / 64; ++w) {
+        lo_x = fmin(lo_x, box[0][w]);
+        lo_y = fmin(lo_y, box[1][w]);
+        lo_z = fmin(lo_z, box[2][w]);
+        hi_x = fmax(hi_x, box[3][w]);
+        hi_y = fmax(hi_y, box[4][w]);
+        hi_z = fmax(hi_z, box[5][w]);
+    }
+    lo_x = uniform(lo_x);
+    lo_y = uniform(lo_y);
+    lo_z = uniform(lo_z);
+    hi_x = uniform(hi_x);
+    hi_y = uniform(hi_y);
+    hi_z = uniform(hi_z);
+    // Every lane now holds the same box.  A box of non-finite positions
+    // gives a NaN origin; the field is then NaN, and the step kernel flags it.
+    const double ox = 0.5 * (lo_x + hi_x), oy = 0.5 * (lo_y + hi_y), oz = 0.5 * (lo_z + hi_z);
+    const double hx = 0.5 * (hi_x - lo_x), hy = 0.5 * (hi_y - lo_y), hz = 0.5 * (hi_z - lo_z);
+    const double rc2d = 0.0625 * (hx * hx + hy * hy + hz * hz);  // (rho / 4)^2
+    const float rc2 = uniform((float)rc2d);
 
     float thx[TPT], thy[TPT], thz[TPT], tlx[TPT], tly[TPT], tlz[TPT];
     float ax[TPT], ay[TPT], az[TPT];
 #pragma unroll
     for (int t = 0; t < TPT; ++t) {
-        uint32_t slot = tbase + (uint32_t)(t * kFieldThreads + tid);
-        double px = 0.0, py = 0.0, pz = 0.0;
-        if (slot < nt) {
-            uint32_t j = a.tlist ? (uint32_t)a.tlist[slot] : slot;
-            px = a.x[j];
-            py = a.y[j];
-            pz = a.z[j];
-        }
-        thx[t] = (float)px;
-        thy[t] = (float)py;
-        thz[t] = (float)pz;
-        tlx[t] = (float)(px - (double)thx[t]);
-        tly[t] = (float)(py - (double)thy[t]);
-        tlz[t] = (float)(pz - (double)thz[t]);
+        const double rx = px[t] - ox, ry = py[t] - oy, rz = pz[t] - oz;
+        thx[t] = (float)rx;
+        thy[t] = (float)ry;
+        thz[t] = (float)rz;
+        tlx[t] = (float)(rx - (double)thx[t]);
+        tly[t] = (float)(ry - (double)thy[t]);
+        tlz[t] = (float)(rz - (double)thz[t]);
         ax[t] = 0.0f;
         ay[t] = 0.0f;
         az[t] = 0.0f;
     }
 
     double qx = 0.0, qy = 0.0, qz = 0.0;  // this lane's source of the next tile
-    auto fetch = [&](uint32_t tile) {
-        uint32_t i = tile + (uint32_t)tid;
-        qx = qy = qz = 0.0;
-        if (i < s_end) {
-            uint32_t c = a.slist ? (uint32_t)a.slist[i] : i;
-            qx = a.x[c];
-            qy = a.y[c];
-            qz = a.z[c];
+    double qb = 0.0;                      // lanes 0-5: one bound of that tile's box
+    auto fetch = [&](uint32_t t) {
+        const uint32_t i = t * kTile + (uint32_t)tid;
+        qx = ox;
+        qy = oy;
+        qz = oz;
+        if (i < ns) {
+            qx = a.sx[i];
+            qy = a.sy[i];
+            qz = a.sz[i];
         }
+        if (a.tile_box && tid < 6) qb = a.tile_box[(size_t)tid * a.tile_stride + t];
     };
     auto stage = [&](int b) {
-        float hx = (float)qx, hy = (float)qy, hz = (float)qz;
-        sh[b][0][tid] = hx;
-        sh[b][1][tid] = hy;
-        sh[b][2][tid] = hz;
-        sh[b][3][tid] = (float)(qx - (double)hx);
-        sh[b][4][tid] = (float)(qy - (double)hy);
-        sh[b][5][tid] = (float)(qz - (double)hz);
+        if (tid < 6) tbox[b][tid] = qb;
+        const double rx = qx - ox, ry = qy - oy, rz = qz - oz;
+        const float fx = (float)rx, fy = (float)ry, fz = (float)rz;
+        sh[b][0][tid] = fx;
+        sh[b][1][tid] = fy;
+        sh[b][2][tid] = fz;
+        sh[b][3][tid] = (float)(rx - (double)fx);
+        sh[b][4][tid] = (float)(ry - (double)fy);
+        sh[b][5][tid] = (float)(rz - (double)fz);
     };
 
     int buf = 0;
-    if (s_begin < s_end) {
-        fetch(s_begin);
+    if ((uint32_t)chunk < ntiles) {
+        fetch((uint32_t)chunk);
         stage(0);
     }
     __syncthreads();
-    for (uint32_t tile = s_begin; tile < s_end; tile += kTile) {
-        const uint32_t next = tile + kTile;
-        if (next < s_end) fetch(next);
-        const uint32_t cnt = min((uint32_t)kTile, s_end - tile);
+    for (uint32_t t = (uint32_t)chunk; t < ntiles; t += step_t) {
+        const uint32_t next = t + step_t;
+        if (next < ntiles) fetch(next);
+        const uint32_t cnt = min((uint32_t)kTile, ns - t * kTile);
 
         float bx[TPT], by[TPT], bz[TPT];
 #pragma unroll
@@ -132,26 +317,22 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles(FieldArgs a) {
         const float* lxp = sh[buf][3];
         const float* lyp = sh[buf][4];
         const float* lzp = sh[buf][5];
-        uint32_t k = 0;
-        for (; k + 4 <= cnt; k += 4) {
-            float4 hx = *reinterpret_cast<const float4*>(hxp + k);
-            float4 hy = *reinterpret_cast<const float4*>(hyp + k);
-            float4 hz = *reinterpret_cast<const float4*>(hzp + k);
-            float4 lx = *reinterpret_cast<const float4*>(lxp + k);
-            float4 ly = *reinterpret_cast<const float4*>(lyp + k);
-            float4 lz = *reinterpret_cast<const float4*>(lzp + k);
-            pair_terms<TPT>(hx.x, hy.x, hz.x, lx.x, ly.x, lz.x, thx, thy, thz, tlx, tly, tlz,
-                            a.eps2, bx, by, bz);
-            pair_terms<TPT>(hx.y, hy.y, hz.y, lx.y, ly.y, lz.y, thx, thy, thz, tlx, tly, tlz,
-                            a.eps2, bx, by, bz);
-            pair_terms<TPT>(hx.z, hy.z, hz.z, lx.z, ly.z, lz.z, thx, thy, thz, tlx, tly, tlz,
-                            a.eps2, bx, by, bz);
-            pair_terms<TPT>(hx.w, hy.w, hz.w, lx.w, ly.w, lz.w, thx, thy, thz, tlx, tly, tlz,
-                            a.eps2, bx, by, bz);
+        // A tile whose bounding box is at least rho/4 from the targets' box
+        // cannot hold a close pair: its pairs skip the per-pair check.
+        bool far_tile = false;
+        if (a.tile_box) {
+            const double* tb = tbox[buf];
+            const double gx = fmax(0.0, fmax(tb[0] - hi_x, lo_x - tb[3]));
+            const double gy = fmax(0.0, fmax(tb[1] - hi_y, lo_y - tb[4]));
+            const double gz = fmax(0.0, fmax(tb[2] - hi_z, lo_z - tb[5]));
+            far_tile = gx * gx + gy * gy + gz * gz >= rc2d;
         }
-        for (; k < cnt; ++k) {
-            pair_terms<TPT>(hxp[k], hyp[k], hzp[k], lxp[k], lyp[k], lzp[k], thx, thy, thz, tlx,
-                            tly, tlz, a.eps2, bx, by, bz);
+        if (far_tile) {
+            tile_terms<TPT, false>(hxp, hyp, hzp, lxp, lyp, lzp, cnt, thx, thy, thz, tlx, tly, tlz,
+                                   a.eps2, rc2, bx, by, bz);
+        } else {
+            tile_terms<TPT, true>(hxp, hyp, hzp, lxp, lyp, lzp, cnt, thx, thy, thz, tlx, tly, tlz,
+                                  a.eps2, rc2, bx, by, bz);
         }
 #pragma unroll
         for (int t = 0; t < TPT; ++t) {
@@ -159,23 +340,83 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles(FieldArgs a) {
             ay[t] += by[t];
             az[t] += bz[t];
         }
-        if (next < s_end) stage(buf ^ 1);
+        if (next < ntiles) stage(buf ^ 1);
         __syncthreads();
         buf ^= 1;
     }
 
-    float* px = a.part + (size_t)(chunk * 3 + 0) * a.pstride;
-    float* py = a.part + (size_t)(chunk * 3 + 1) * a.pstride;
-    float* pz = a.part + (size_t)(chunk * 3 + 2) * a.pstride;
+    float* outx = a.part + (size_t)(chunk * 3 + 0) * a.pstride;
+    float* outy = a.part + (size_t)(chunk * 3 + 1) * a.pstride;
+    float* outz = a.part + (size_t)(chunk * 3 + 2) * a.pstride;
 #pragma unroll
     for (int t = 0; t < TPT; ++t) {
-        uint32_t slot = tbase + (uint32_t)(t * kFieldThreads + tid);
+        const uint32_t slot = tbase + (uint32_t)(t * kFieldThreads + tid);
         if (slot < nt) {
-            px[slot] = ax[t];
-            py[slot] = ay[t];
-            pz[slot] = az[t];
+            outx[slot] = ax[t];
+            outy[slot] = ay[t];
+            outz[slot] = az[t];
         }
     }
+}
+
+// Positions of a key list gathered into slot order, and the bounding box
+// (FP64, absolute coordinates) of each tile of kTile consecutive slots:
+// box[k * stride + tile], k = lo x, y, z, hi x, y, z.  One workgroup per tile.
+__global__ __launch_bounds__(kTile) void gather_tiles(const uint64_t* keys, const uint32_t* count,
+                                                      uint32_t count_c, uint64_t idx_mask,
+                                                      uint32_t n_all, const double* x,
+                                                      const double* y, const double* z,
+                                                      double* px, double* py, double* pz,
+                                                      double* box, uint32_t stride) {
+    __shared__ double red[6][kTile / 64];
+    const uint32_t ns = count ? *count : count_c;
+    const uint32_t tile = blockIdx.x;
+    if (tile * kTile >= ns) return;  // uniform per workgroup
+    const uint32_t i = tile * kTile + threadIdx.x;
+    double lx = INFINITY, ly = INFINITY, lz = INFINITY;
+    double hx = -INFINITY, hy = -INFINITY, hz = -INFINITY;
+    if (i < ns) {
+        // a list only holds real keys below its count; the clamp keeps every
+        // load inside the arrays regardless
+        const uint32_t c = min((uint32_t)(keys[i] & idx_mask), n_all - 1u);
+        lx = hx = px[i] = x[c];
+        ly = hy = py[i] = y[c];
+        lz = hz = pz[i] = z[c];
+    }
+    if (!box) return;
+    lx = wave_min(lx);
+    ly = wave_min(ly);
+    lz = wave_min(lz);
+    hx = wave_max(hx);
+    hy = wave_max(hy);
+    hz = wave_max(hz);
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][wave] = lx;
+        red[1][wave] = ly;
+        red[2][wave] = lz;
+        red[3][wave] = hx;
+        red[4][wave] = hy;
+        red[5][wave] = hz;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int k = threadIdx.x;
+        double v = red[k][0];
+        for (int w = 1; w < kTile / 64; ++w) v = (k < 3) ? fmin(v, red[k][w]) : fmax(v, red[k][w]);
+        box[(size_t)k * stride + tile] = v;
+    }
+}
+
+hipError_t launch_gather(const uint64_t* keys, const uint32_t* count, uint32_t count_c,
+                         uint32_t bound, uint64_t idx_mask, uint32_t n_all, const double* x,
+                         const double* y, const double* z, double* px, double* py, double* pz,
+                         double* box, uint32_t stride, hipStream_t s) {
+    const uint32_t tiles = (bound + kTile - 1) / kTile;
+    if (tiles == 0) return hipSuccess;
+    gather_tiles<<<tiles, kTile, 0, s>>>(keys, count, count_c, idx_mask, n_all, x, y, z, px, py,
+                                         pz, box, stride);
+    return hipGetLastError();
 }
 
 hipError_t launch_field(const FieldArgs& a, int tpt, uint32_t nt_bound, hipStream_t s) {
@@ -244,13 +485,19 @@ __global__ __launch_bounds__(kStepThreads) void step_update(StepArgs a) {
     }
     const int lane = threadIdx.x & 63;
     const double two_pi = 6.283185307179586476925286766559;
-    for (uint32_t base = blockIdx.x * kStepThreads; base < n_in;
+    const uint64_t idx_mask = (1ull << a.idx_bits) - 1ull;
+    // Full list: every carrier keeps its slot (collected ones copy their key
+    // through) and the next sort restores the order.  Otherwise: the
+    // travelling holes are appended, one atomic per wave.
+    const uint32_t limit = a.full_list ? a.n_all : n_in;
+    for (uint32_t base = blockIdx.x * kStepThreads; base < limit;
          base += gridDim.x * kStepThreads) {
         const uint32_t slot = base + threadIdx.x;
         bool keep = false;
         int32_t j = 0;
+        uint64_t key = kNoKey;
         if (slot < n_in) {
-            j = a.list_in[slot];
+            j = (int32_t)min((uint32_t)(a.keys_in[slot] & idx_mask), a.n_all - 1u);
             double ecx = 0.0, ecy = 0.0, ecz = 0.0;
             if (a.coulomb) {
                 double sx = 0.0, sy = 0.0, sz = 0.0;
@@ -293,22 +540,25 @@ __global__ __launch_bounds__(kStepThreads) void step_update(StepArgs a) {
             a.y[j] = yn;
             a.z[j] = zn;
             if (!isfinite(xn) || !isfinite(yn) || !isfinite(zn)) atomicOr(&a.misc[0], 1);
-            if (zn <= a.z_well) {
-                a.cstep[j] = (int32_t)(a.step + 1u);
-            } else {
-                keep = true;
-            }
+            const bool collected = zn <= a.z_well;
+            if (collected) a.cstep[j] = (int32_t)(a.step + 1u);
+            keep = !collected;
+            key = spatial_key(xn, yn, zn, (uint32_t)j, a.idx_bits, collected);
+        } else if (slot < limit) {
+            key = a.keys_in[slot];  // collected: frozen, key unchanged
         }
         const unsigned long long m = __ballot(keep);
+        uint32_t wbase = 0;
         if (m) {
             const int leader = __ffsll((long long)m) - 1;
-            uint32_t wbase = 0;
             if (lane == leader) wbase = atomicAdd(a.cnt_out, (uint32_t)__popcll(m));
             wbase = __shfl(wbase, leader);
-            if (keep) {
-                const unsigned long long below = (lane == 0) ? 0ull : (m << (64 - lane));
-                a.list_out[wbase + (uint32_t)__popcll(below)] = j;
-            }
+        }
+        if (a.full_list) {
+            if (slot < limit) a.keys_out[slot] = key;
+        } else if (keep) {
+            const unsigned long long below = (lane == 0) ? 0ull : (m << (64 - lane));
+            a.keys_out[wbase + (uint32_t)__popcll(below)] = key;
         }
     }
 }
@@ -321,7 +571,8 @@ static uint32_t grid_for(uint64_t n, int threads, uint32_t cap) {
 }
 
 hipError_t launch_step(const StepArgs& a, uint32_t n_bound, hipStream_t s) {
-    step_update<<<grid_for(n_bound, kStepThreads, 8192), kStepThreads, 0, s>>>(a);
+    const uint32_t slots = a.full_list ? a.n_all : n_bound;
+    step_update<<<grid_for(slots, kStepThreads, 8192), kStepThreads, 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -330,42 +581,59 @@ hipError_t launch_step(const StepArgs& a, uint32_t n_bound, hipStream_t s) {
 // holes at or below the well (collection step 0), list the others.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kStepThreads) void load_prepare(double* z, int32_t* cstep,
-                                                             int32_t* list, uint32_t* cnt,
-                                                             uint32_t n, double thickness,
+                                                             uint64_t* keys, uint32_t* cnt,
+                                                             const double* x, const double* y,
+                                                             uint32_t n, uint32_t idx_bits,
+                                                             int full_list, double thickness,
                                                              double z_well) {
     const int lane = threadIdx.x & 63;
     for (uint32_t base = blockIdx.x * kStepThreads; base < n; base += gridDim.x * kStepThreads) {
         const uint32_t j = base + threadIdx.x;
         bool keep = false;
+        uint64_t key = kNoKey;
         if (j < n) {
             double zz = z[j];
             if (zz > thickness) zz = 2.0 * thickness - zz;
             z[j] = zz;
-            if (zz <= z_well) {
-                cstep[j] = 0;
-            } else {
-                cstep[j] = -1;
-                keep = true;
-            }
+            const bool collected = zz <= z_well;
+            cstep[j] = collected ? 0 : -1;
+            keep = !collected;
+            key = spatial_key(x[j], y[j], zz, j, idx_bits, collected);
         }
         const unsigned long long m = __ballot(keep);
+        uint32_t wbase = 0;
         if (m) {
             const int leader = __ffsll((long long)m) - 1;
-            uint32_t wbase = 0;
             if (lane == leader) wbase = atomicAdd(cnt, (uint32_t)__popcll(m));
             wbase = __shfl(wbase, leader);
-            if (keep) {
-                const unsigned long long below = (lane == 0) ? 0ull : (m << (64 - lane));
-                list[wbase + (uint32_t)__popcll(below)] = (int32_t)j;
-            }
+        }
+        if (full_list) {
+            if (j < n) keys[j] = key;
+        } else if (keep) {
+            const unsigned long long below = (lane == 0) ? 0ull : (m << (64 - lane));
+            keys[wbase + (uint32_t)__popcll(below)] = key;
         }
     }
 }
 
-hipError_t launch_load(double* z, int32_t* cstep, int32_t* list, uint32_t* cnt, uint32_t n,
+hipError_t launch_load(double* z, int32_t* cstep, uint64_t* keys, uint32_t* cnt, const double* x,
+                       const double* y, uint32_t n, uint32_t idx_bits, int full_list,
                        double thickness, double z_well, hipStream_t s) {
-    load_prepare<<<grid_for(n, kStepThreads, 8192), kStepThreads, 0, s>>>(z, cstep, list, cnt, n,
-                                                                          thickness, z_well);
+    load_prepare<<<grid_for(n, kStepThreads, 8192), kStepThreads, 0, s>>>(
+        z, cstep, keys, cnt, x, y, n, idx_bits, full_list, thickness, z_well);
+    return hipGetLastError();
+}
+
+// Keys of every carrier, in carrier order (targets of gccd_field).
+__global__ void keys_all(const double* x, const double* y, const double* z, uint32_t n,
+                         uint32_t idx_bits, uint64_t* keys) {
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x)
+        keys[j] = spatial_key(x[j], y[j], z[j], j, idx_bits, false);
+}
+
+hipError_t launch_keys_all(const double* x, const double* y, const double* z, uint32_t n,
+                           uint32_t idx_bits, uint64_t* keys, hipStream_t s) {
+    keys_all<<<grid_for(n, 256, 8192), 256, 0, s>>>(x, y, z, n, idx_bits, keys);
     return hipGetLastError();
 }
 
@@ -381,26 +649,44 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
     return hipGetLastError();
 }
 
+__global__ void fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    fill_u64<<<grid_for(n, 256, 4096), 256, 0, s>>>(p, n, v);
+    return hipGetLastError();
+}
+
 // Coulomb field of every carrier for gccd_field: chunk partials summed in
-// FP64 in chunk order, times K (same reduction as step_update).
-__global__ void field_finish(const float* part, uint32_t pstride, int nchunk, uint32_t n,
-                             double K, double* ex, double* ey, double* ez) {
-    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+// FP64 in chunk order, times K (same reduction as step_update), written back
+// to the carrier each slot holds.
+__global__ void field_finish(const float* part, uint32_t pstride, int nchunk,
+                             const uint64_t* tkeys, uint64_t idx_mask, uint32_t n, double K,
+                             double* ex, double* ey, double* ez) {
+    for (uint32_t slot = blockIdx.x * blockDim.x + threadIdx.x; slot < n;
+         slot += gridDim.x * blockDim.x) {
         double sx = 0.0, sy = 0.0, sz = 0.0;
         for (int c = 0; c < nchunk; ++c) {
-            sx += (double)part[(size_t)(c * 3 + 0) * pstride + j];
-            sy += (double)part[(size_t)(c * 3 + 1) * pstride + j];
-            sz += (double)part[(size_t)(c * 3 + 2) * pstride + j];
+            sx += (double)part[(size_t)(c * 3 + 0) * pstride + slot];
+            sy += (double)part[(size_t)(c * 3 + 1) * pstride + slot];
+            sz += (double)part[(size_t)(c * 3 + 2) * pstride + slot];
         }
+        const uint32_t j = min((uint32_t)(tkeys[slot] & idx_mask), n - 1u);
         ex[j] = K * sx;
         ey[j] = K * sy;
         ez[j] = K * sz;
     }
 }
 
-hipError_t launch_field_finish(const float* part, uint32_t pstride, int nchunk, uint32_t n,
-                               double K, double* ex, double* ey, double* ez, hipStream_t s) {
-    field_finish<<<grid_for(n, 256, 8192), 256, 0, s>>>(part, pstride, nchunk, n, K, ex, ey, ez);
+hipError_t launch_field_finish(const float* part, uint32_t pstride, int nchunk,
+                               const uint64_t* tkeys, uint64_t idx_mask, uint32_t n, double K,
+                               double* ex, double* ey, double* ez, hipStream_t s) {
+    field_finish<<<grid_for(n, 256, 8192), 256, 0, s>>>(part, pstride, nchunk, tkeys, idx_mask, n,
+                                                         K, ex, ey, ez);
     return hipGetLastError();
 }
 

@@ -90,7 +90,7 @@ def test_field_cloud_1000_all_targets(g, W, orc):
     assert ea <= FIELD_TOL
 
 
-@pytest.mark.parametrize("tpt,chunks", [(1, 1), (2, 1), (4, 1), (1, 3), (2, 8), (4, 32), (0, 0)])
+@pytest.mark.parametrize("tpt,chunks", [(1, 1), (2, 1), (4, 1), (1, 3), (2, 8), (4, 32), (1, 64), (0, 0)])
 def test_field_ragged_launch_shapes(g, W, orc, tpt, chunks):
     """5003 carriers: several LDS tiles, a ragged last tile and target block,
     and source chunks of unequal length."""
