@@ -80,8 +80,10 @@ typedef struct {
     uint64_t pair_interactions;/* sum over steps of targets x sources of Eq. (6)      */
     double field_ms;           /* device time in the Eq. (6) kernel (timing on only)  */
     int64_t field_launches;    /* launches of that kernel while timing was on        */
-    int32_t targets_per_thread;/* launch shape of the last Eq. (6) launch            */
-    int32_t source_chunks;
+    int32_t targets_per_thread;/* launch shape of the Eq. (6) launches               */
+    int32_t source_chunks;     /* source chunks of event 0's field sum               */
+    int64_t n_events;          /* events loaded                                       */
+    int64_t max_source_chunks; /* largest source split over all events               */
 } gccd_stats_t;
 
 /* Creates a context bound to the current HIP device and to hip_stream (a
@@ -96,10 +98,23 @@ int gccd_init(const gccd_params* p, void* hip_stream, gccd_ctx** out);
  * that are already resident in device memory): x, y, z are device arrays of n FP64
  * positions in um, copied into the context.  A z beyond the back surface is
  * mirrored back; a z at or below the well is collected at step 0.  Resets the
- * step counter and every statistic.  GCCD_E_INVALID for n <= 0, n > 2^27
- * or a NULL pointer; GCCD_E_NOMEM if buffers cannot be allocated.  Non-finite
+ * step counter and every statistic.  Synchronises the stream.
+ * GCCD_E_INVALID for n <= 0, n > 2^27 or a NULL pointer; GCCD_E_NOMEM if buffers cannot be allocated.  Non-finite
  * input positions make the next gccd_run return GCCD_E_NONFINITE. */
 int gccd_load(gccd_ctx* c, int64_t n, const double* x, const double* y, const double* z);
+
+/* Loads n_events independent events (each a separate cloud or track whose
+ * holes repel only each other): offsets is a HOST array of n_events + 1
+ * carrier offsets (offsets[0] = 0, strictly increasing, every event at least
+ * one carrier); x, y, z are device arrays of offsets[n_events] FP64
+ * positions, event e occupying [offsets[e], offsets[e+1]).  Event e draws
+ * its diffusion steps with Philox counter (carrier index within the event,
+ * step, params.event + e, 0), so each event evolves exactly as if it were
+ * loaded alone with params.event + e.  Otherwise as gccd_load, which is the
+ * one-event case.  GCCD_E_INVALID for bad offsets, more than 2^31-1 carriers
+ * in total, or when the event count times the largest event exceeds 2^27. */
+int gccd_load_events(gccd_ctx* c, int32_t n_events, const int64_t* offsets, const double* x,
+                     const double* y, const double* z);
 
 /* Advances the simulation (Sec. III.B, Fig. 2) by up to max_steps time steps
  * of dt_ps picoseconds.  Each step computes, for every travelling hole, the
@@ -129,11 +144,18 @@ int gccd_run(gccd_ctx* c, double dt_ps, int64_t max_steps, int64_t* steps_done,
 int gccd_image(gccd_ctx* c, double x0_um, double y0_um, double pitch_um, int32_t nx,
                int32_t ny, uint32_t* counts, uint64_t* n_outside);
 
+/* As gccd_image, with one grid per event: counts is a device array of
+ * n_events*ny*nx uint32 (event major), n_outside a device array of n_events
+ * uint64. */
+int gccd_image_events(gccd_ctx* c, double x0_um, double y0_um, double pitch_um, int32_t nx,
+                      int32_t ny, uint32_t* counts, uint64_t* n_outside);
+
 /* The Coulomb field of Eq. (6), in V/cm, at every loaded carrier from the
- * current sources (all carriers, or only travelling ones when
- * collected_are_sources is 0), computed by the same kernel and launch shape
- * as gccd_run.  ex, ey, ez are device arrays of n FP64 values.
- * GCCD_E_STATE before load, GCCD_E_INVALID for NULL pointers. */
+ * current sources of its own event (all its carriers, or only travelling ones
+ * when collected_are_sources is 0), computed by the same kernel and source
+ * split as gccd_run.  ex, ey, ez are device arrays of n FP64 values.
+ * Synchronises the stream.  GCCD_E_STATE before load, GCCD_E_INVALID for
+ * NULL pointers. */
 int gccd_field(gccd_ctx* c, double* ex, double* ey, double* ez);
 
 /* Copies the current FP64 positions and collection steps (-1 while a hole
@@ -146,10 +168,12 @@ int gccd_positions(gccd_ctx* c, double* x, double* y, double* z, int32_t* collec
 int gccd_stats(gccd_ctx* c, gccd_stats_t* out);
 
 /* Fixes the launch shape of the Eq. (6) kernel: targets per thread (1, 2 or
- * 4) and the number of source chunks each target's sum is split into (1-64).
- * 0 for either means "choose automatically" (the default).  Results do not
- * depend on the targets per thread; the split changes only the FP32
- * summation order.  GCCD_E_INVALID outside those ranges. */
+ * 4) and the number of source chunks each target's sum is split into (1-64,
+ * the same for every event).  0 for either means "choose automatically" (the
+ * default).  The split changes the FP32 summation order; the targets per
+ * thread change the workgroups' origins and so the rounding of the pair
+ * differences.  Applies to the current load and later ones; synchronises the
+ * stream.  GCCD_E_INVALID outside those ranges. */
 int gccd_set_launch(gccd_ctx* c, int32_t targets_per_thread, int32_t source_chunks);
 
 /* on = 1 times every Eq. (6) launch with HIP events on the context's stream

@@ -1,13 +1,16 @@
 // Host side of the C ABI declared in include/gccd.h: parameter validation,
-// device buffers, the step loop of Sec. III.B (Fig. 2) and its launch shapes.
+// device buffers, the step loop of Sec. III.B (Fig. 2), the spatially sorted
+// carrier list and the work items of the Eq. (6) launch.
 #include "gccd.h"
 #include "gccd_internal.h"
 
-#include <cmath>
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <cmath>
 #include <new>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -21,13 +24,21 @@ constexpr double kKB = 1.380649e-23;
 constexpr double kEps0 = 8.8541878128e-12;
 constexpr double kPi = 3.14159265358979323846;
 
-constexpr int kPoll = 32;  // steps between host reads of the active count
-constexpr int64_t kMaxCarriers = 1ll << 27;  // carrier index fits the low key bits
+constexpr int kPoll = 32;                       // steps between host reads of the counts
+constexpr int64_t kMaxCarriers = 2147483647LL;  // slots are 32-bit
 
-// Small device block of counters: [0..2] active counts (ring of three, by step
-// mod 3), [3] non-finite flag, [4] step after the last step with travelling
-// holes, [8..11] two uint64 statistics.
-constexpr int kMetaWords = 16;
+// Device block of counters (32-bit words): a ring of three travelling-hole
+// counts by step mod 3 (carrier mode), the non-finite flag, the step after
+// the last step with travelling holes, two uint64 statistics and the two
+// uint64 counts of the coming step (list mode).
+enum : int {
+    kMetaCount = 0,
+    kMetaFlag = 3,
+    kMetaLast = 4,
+    kMetaStats = 8,
+    kMetaPending = 12,
+    kMetaWords = 16
+};
 
 }  // namespace
 
@@ -40,37 +51,49 @@ struct gccd_ctx {
     // derived constants
     double K = 0, mu0 = 0, ec = 0, beta = 0, inv_beta = 0, vt = 0;
 
-    int64_t n = 0, cap = 0;
+    // the loaded carriers
+    bool loaded = false;
+    bool list_mode = false;  // Coulomb on: the sorted list drives every step
+    int64_t n = 0;
+    uint32_t n_events = 0;
+    KeyLayout kl{1, 0};
+    std::vector<uint32_t> off_h;   // [E+1] first carrier of each event
+    std::vector<uint32_t> tile_h;  // [E+1] first source tile of each event
+    std::vector<int32_t> chunks_h; // [E] chunks of each event's field sum
+    std::vector<uint32_t> order_h; // events by decreasing size (work-item order)
+    uint32_t n_tiles = 0;
+    int max_chunks = 1;
+
     double* x = nullptr;
     double* y = nullptr;
     double* z = nullptr;
     int32_t* cstep = nullptr;
-    // key lists: keys[cur] holds this step's travelling holes (sorted when
-    // Coulomb is on), keys[cur ^ 1] receives the next step's, keys[2] is
-    // scratch for gccd_field
-    uint64_t* keys[3] = {nullptr, nullptr, nullptr};
+    uint32_t* ev_of = nullptr;
+    uint64_t* keys[2] = {nullptr, nullptr};
     int cur = 0;
-    uint32_t idx_bits = 1;
+    double* ps[3] = {nullptr, nullptr, nullptr};
+    double* tile_box = nullptr;
+    float* part = nullptr;
+    uint32_t* ev_off_d = nullptr;
+    uint32_t* ev_tile_d = nullptr;
+    uint32_t* tile_event_d = nullptr;
+    uint32_t* ev_active_d = nullptr;
+    int32_t* ev_chunks_d = nullptr;
+    FieldItem* items_d = nullptr;
+    size_t items_cap = 0;
+    uint32_t n_items = 0;
     void* sort_tmp = nullptr;
     size_t sort_tmp_bytes = 0;
-    // lists hold all n carriers (Coulomb on, collected holes are sources) or
-    // only the travelling ones
-    bool full_list = false;
-    double* tile_box = nullptr;  // [6][tile_stride] source-tile bounding boxes
-    uint32_t tile_stride = 0;
-    // positions gathered into list-slot order: set 0 for the run's list (the
-    // Eq. (6) sources, and its targets), set 1 for gccd_field's targets
-    double* ps[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
-    float* part = nullptr;
     uint32_t* meta = nullptr;
-    uint32_t* host_meta = nullptr;  // pinned
+    uint32_t* host_meta = nullptr;    // pinned
+    uint32_t* host_active = nullptr;  // pinned [E]
+    FieldItem* host_items = nullptr;  // pinned [items_cap]
 
-    bool loaded = false;
     int64_t step = 0;
     int64_t n_active = 0;
 
     int tpt_fixed = 0, chunks_fixed = 0;
-    int last_tpt = 0, last_chunks = 0;
+    int tpt = 1;
 
     bool timing = false;
     std::vector<hipEvent_t> ev;
@@ -95,9 +118,9 @@ int fail(gccd_ctx* c, int status, const char* what, hipError_t e = hipSuccess) {
     return status;
 }
 
-#define GCCD_HIP(ctx, call)                                              \
-    do {                                                                 \
-        hipError_t e_ = (call);                                          \
+#define GCCD_HIP(ctx, call)                                                  \
+    do {                                                                     \
+        hipError_t e_ = (call);                                              \
         if (e_ != hipSuccess) return fail((ctx), GCCD_E_DEVICE, #call, e_); \
     } while (0)
 
@@ -119,58 +142,122 @@ int validate(const gccd_params* p) {
     return GCCD_OK;
 }
 
-void free_buffers(gccd_ctx* c) {
-    (void)hipFree(c->x);
-    (void)hipFree(c->y);
-    (void)hipFree(c->z);
-    (void)hipFree(c->cstep);
-    for (int i = 0; i < 3; ++i) (void)hipFree(c->keys[i]);
-    (void)hipFree(c->sort_tmp);
-    (void)hipFree(c->tile_box);
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 3; ++b) {
-            (void)hipFree(c->ps[a][b]);
-            c->ps[a][b] = nullptr;
-        }
-    (void)hipFree(c->part);
-    c->x = c->y = c->z = nullptr;
-    c->cstep = nullptr;
-    c->keys[0] = c->keys[1] = c->keys[2] = nullptr;
-    c->sort_tmp = nullptr;
-    c->sort_tmp_bytes = 0;
-    c->tile_box = nullptr;
-    c->tile_stride = 0;
-    c->part = nullptr;
-    c->cap = 0;
+template <typename T>
+void dfree(T*& ptr) {
+    (void)hipFree(ptr);
+    ptr = nullptr;
 }
 
-// Launch shape of Eq. (6) for up to nt targets and ns sources: enough
-// workgroups to give every CU several of them (splitting the sources into
-// chunks when the targets alone are too few), and at least a few LDS tiles per
-// chunk.  The split fixes the FP32 summation order, so it is chosen from the
-// loaded carrier count only -- never from how many are still travelling --
-// and every step of a load, and gccd_field, sums in the same order.
-void choose_shape(const gccd_ctx* c, uint32_t nt, uint32_t ns, int* tpt, int* chunks) {
-    // One target per lane: the smallest workgroup box, hence the fewest
-    // close pairs taking the exact-difference branch, and 62 VGPRs (eight
-    // waves per SIMD).  Measured faster than two or four per lane.
-    int t = c->tpt_fixed ? c->tpt_fixed : 1;
-    int s = c->chunks_fixed;
-    if (s == 0) {
-        const uint64_t per_block = (uint64_t)kFieldThreads * t;
-        const uint64_t tblocks = (nt + per_block - 1) / per_block;
-        // about 48 waves per SIMD in total (6 rounds of 8 resident), which
-        // evens out workgroups whose boxes see more close pairs
-        const uint64_t want = (uint64_t)c->n_cu * 48;
-        uint64_t k = tblocks ? (want + tblocks - 1) / tblocks : 1;
-        const uint64_t by_tiles = ns / (4u * kTile);  // keep >= 4 tiles per chunk
-        if (k > by_tiles) k = by_tiles;
-        if (k < 1) k = 1;
-        if (k > (uint64_t)kMaxChunks) k = kMaxChunks;
-        s = (int)k;
+template <typename T>
+void hfree(T*& ptr) {
+    (void)hipHostFree(ptr);
+    ptr = nullptr;
+}
+
+void free_buffers(gccd_ctx* c) {
+    dfree(c->x);
+    dfree(c->y);
+    dfree(c->z);
+    dfree(c->cstep);
+    dfree(c->ev_of);
+    dfree(c->keys[0]);
+    dfree(c->keys[1]);
+    for (auto& q : c->ps) dfree(q);
+    dfree(c->tile_box);
+    dfree(c->part);
+    dfree(c->ev_off_d);
+    dfree(c->ev_tile_d);
+    dfree(c->tile_event_d);
+    dfree(c->ev_active_d);
+    dfree(c->ev_chunks_d);
+    dfree(c->items_d);
+    dfree(c->sort_tmp);
+    hfree(c->host_active);
+    hfree(c->host_items);
+    c->items_cap = 0;
+    c->sort_tmp_bytes = 0;
+    c->loaded = false;
+}
+
+uint32_t bits_for(uint64_t count) {  // smallest b with 2^b >= count (0 for count <= 1)
+    uint32_t b = 0;
+    while ((1ull << b) < count) ++b;
+    return b;
+}
+
+// Source chunks of each event's sum.  The split fixes the FP32 summation
+// order, so it depends on the loaded sizes only, never on how many holes
+// still travel: every step of a load, and gccd_field, sum in the same order.
+// Enough workgroups to fill the chip (about 48 waves per SIMD in total,
+// which also evens out workgroups that meet more close pairs), at most 3072
+// sources per chunk, and at least 4 tiles per chunk.
+void choose_chunks(gccd_ctx* c) {
+    uint64_t tblocks = 0;
+    for (uint32_t e = 0; e < c->n_events; ++e)
+        tblocks += (c->off_h[e + 1] - c->off_h[e] + kFieldThreads * c->tpt - 1) /
+                   (kFieldThreads * c->tpt);
+    const uint64_t want = (uint64_t)c->n_cu * 48;
+    c->chunks_h.assign(c->n_events, 1);
+    c->max_chunks = 1;
+    for (uint32_t e = 0; e < c->n_events; ++e) {
+        const uint64_t ne = c->off_h[e + 1] - c->off_h[e];
+        const uint64_t tiles = (ne + kTile - 1) / kTile;
+        uint64_t s;
+        if (c->chunks_fixed) {
+            s = (uint64_t)c->chunks_fixed;
+        } else {
+            s = std::max<uint64_t>((ne + 3071) / 3072, (want + tblocks - 1) / tblocks);
+            s = std::min<uint64_t>(s, std::max<uint64_t>(1, tiles / 4));
+            s = std::min<uint64_t>(s, kMaxChunks);
+            s = std::max<uint64_t>(s, 1);
+        }
+        c->chunks_h[e] = (int32_t)s;
+        c->max_chunks = std::max(c->max_chunks, (int)s);
     }
-    *tpt = t;
-    *chunks = s;
+}
+
+// Work items for targets bound[e] of each event: largest events first, so the
+// longest workgroups start early.
+int build_items(gccd_ctx* c, const uint32_t* bound) {
+    const uint32_t per = (uint32_t)(kFieldThreads * c->tpt);
+    size_t k = 0;
+    for (uint32_t e : c->order_h) {
+        const uint32_t blocks = (bound[e] + per - 1) / per;
+        const uint32_t s = (uint32_t)c->chunks_h[e];
+        for (uint32_t b = 0; b < blocks; ++b)
+            for (uint32_t ch = 0; ch < s; ++ch) {
+                if (k >= c->items_cap) return fail(c, GCCD_E_DEVICE, "work item overflow");
+                c->host_items[k++] = FieldItem{e, b, ch, s};
+            }
+    }
+    c->n_items = (uint32_t)k;
+    if (k) {
+        GCCD_HIP(c, hipMemcpyAsync(c->items_d, c->host_items, k * sizeof(FieldItem),
+                                   hipMemcpyHostToDevice, c->stream));
+    }
+    return GCCD_OK;
+}
+
+// Partial-sum buffer and work-item capacity for the current chunk choice.
+int size_chunk_buffers(gccd_ctx* c) {
+    dfree(c->part);
+    dfree(c->items_d);
+    hfree(c->host_items);
+    size_t items = 0;
+    for (uint32_t e = 0; e < c->n_events; ++e) {
+        const uint64_t ne = c->off_h[e + 1] - c->off_h[e];
+        items += (size_t)((ne + kFieldThreads - 1) / kFieldThreads) * (size_t)c->chunks_h[e];
+    }
+    c->items_cap = std::max<size_t>(items, 1);
+    if (hipMalloc(&c->part, (size_t)c->max_chunks * 3 * (size_t)c->n * sizeof(float)) !=
+            hipSuccess ||
+        hipMalloc(&c->items_d, c->items_cap * sizeof(FieldItem)) != hipSuccess ||
+        hipHostMalloc((void**)&c->host_items, c->items_cap * sizeof(FieldItem)) != hipSuccess)
+        return fail(c, GCCD_E_NOMEM, "device allocation of the field buffers failed");
+    GCCD_HIP(c, hipMemcpyAsync(c->ev_chunks_d, c->chunks_h.data(), c->n_events * sizeof(int32_t),
+                               hipMemcpyHostToDevice, c->stream));
+    GCCD_HIP(c, hipStreamSynchronize(c->stream));
+    return GCCD_OK;
 }
 
 int record_field_start(gccd_ctx* c, hipEvent_t** pair) {
@@ -198,6 +285,62 @@ int collect_timing(gccd_ctx* c) {
         ++c->field_launches;
     }
     c->ev_used = 0;
+    return GCCD_OK;
+}
+
+uint64_t meta64(const gccd_ctx* c, int word) {
+    uint64_t v;
+    memcpy(&v, c->host_meta + word, sizeof v);
+    return v;
+}
+
+FieldArgs field_args(const gccd_ctx* c, bool targets_all) {
+    FieldArgs fa{};
+    fa.items = c->items_d;
+    fa.ev_off = c->ev_off_d;
+    fa.ev_active = c->ev_active_d;
+    fa.ev_tile = c->ev_tile_d;
+    fa.targets_all = targets_all ? 1 : 0;
+    fa.sources_all = c->p.collected_are_sources;
+    fa.px = c->ps[0];
+    fa.py = c->ps[1];
+    fa.pz = c->ps[2];
+    fa.tile_box = c->tile_box;
+    fa.tile_stride = std::max<uint32_t>(c->n_tiles, 1);
+    fa.eps2 = (float)(c->p.softening_um * c->p.softening_um);
+    fa.part = c->part;
+    fa.pstride = (uint32_t)c->n;
+    return fa;
+}
+
+// The sorted list from keys already written to keys[cur ^ 1]: sort into
+// keys[cur], count each event's travelling holes, gather the positions.
+int finish_list(gccd_ctx* c) {
+    const uint32_t n = (uint32_t)c->n;
+    const uint32_t end_bit = c->kl.lbits + kMortonBits + 1 + c->kl.ebits;
+    GCCD_HIP(c, sort_keys(c->sort_tmp, c->sort_tmp_bytes, c->keys[c->cur ^ 1], c->keys[c->cur], n,
+                          end_bit, c->stream));
+    GCCD_HIP(c, launch_fill_u32(c->meta + kMetaPending, 4, 0u, c->stream));
+    GCCD_HIP(c, launch_count(c->keys[c->cur], c->ev_off_d, c->n_events, c->kl,
+                             c->p.collected_are_sources,
+                             c->ev_active_d,
+                             reinterpret_cast<unsigned long long*>(c->meta + kMetaPending),
+                             c->stream));
+    GCCD_HIP(c, launch_gather(c->keys[c->cur], c->ev_off_d, c->ev_tile_d, c->tile_event_d,
+                              c->ev_active_d, c->p.collected_are_sources, c->n_tiles, c->kl, c->x,
+                              c->y, c->z, c->ps[0], c->ps[1], c->ps[2], c->tile_box,
+                              std::max<uint32_t>(c->n_tiles, 1), c->stream));
+    return GCCD_OK;
+}
+
+int read_counts(gccd_ctx* c) {
+    GCCD_HIP(c, hipMemcpyAsync(c->host_meta, c->meta, kMetaWords * sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, c->stream));
+    if (c->list_mode)
+        GCCD_HIP(c, hipMemcpyAsync(c->host_active, c->ev_active_d,
+                                   c->n_events * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                   c->stream));
+    GCCD_HIP(c, hipStreamSynchronize(c->stream));
     return GCCD_OK;
 }
 
@@ -271,76 +414,125 @@ void gccd_destroy(gccd_ctx* c) {
     delete c;
 }
 
-int gccd_load(gccd_ctx* c, int64_t n, const double* x, const double* y, const double* z) {
+int gccd_load_events(gccd_ctx* c, int32_t n_events, const int64_t* offsets, const double* x,
+                     const double* y, const double* z) {
     if (!c) return GCCD_E_INVALID;
-    if (n <= 0 || n > kMaxCarriers || !x || !y || !z)
-        return fail(c, GCCD_E_INVALID, "gccd_load: n out of range or NULL pointer");
-    uint32_t bits = 1;
-    while ((1ll << bits) < n) ++bits;
-    if (n > c->cap) {
-        GCCD_HIP(c, hipStreamSynchronize(c->stream));
+    if (n_events < 1 || !offsets || !x || !y || !z)
+        return fail(c, GCCD_E_INVALID, "gccd_load_events: no events or NULL pointer");
+    if (offsets[0] != 0) return fail(c, GCCD_E_INVALID, "gccd_load_events: offsets[0] != 0");
+    int64_t max_ne = 0;
+    for (int32_t e = 0; e < n_events; ++e) {
+        const int64_t ne = offsets[e + 1] - offsets[e];
+        if (ne < 1) return fail(c, GCCD_E_INVALID, "gccd_load_events: an event has no carrier");
+        max_ne = std::max(max_ne, ne);
+    }
+    const int64_t n = offsets[n_events];
+    if (n > kMaxCarriers) return fail(c, GCCD_E_INVALID, "gccd_load_events: too many carriers");
+    const KeyLayout kl{std::max<uint32_t>(1, bits_for((uint64_t)max_ne)),
+                       bits_for((uint64_t)n_events)};
+    if (kl.lbits + kl.ebits > (uint32_t)kMaxKeyPayload)
+        return fail(c, GCCD_E_INVALID,
+                    "gccd_load_events: events x largest event exceed 2^27 key space");
+
+    GCCD_HIP(c, hipStreamSynchronize(c->stream));
+    free_buffers(c);
+    c->n = n;
+    c->n_events = (uint32_t)n_events;
+    c->kl = kl;
+    c->tpt = c->tpt_fixed ? c->tpt_fixed : 1;
+    c->off_h.resize(n_events + 1);
+    c->tile_h.resize(n_events + 1);
+    c->tile_h[0] = 0;
+    for (int32_t e = 0; e <= n_events; ++e) c->off_h[e] = (uint32_t)offsets[e];
+    for (int32_t e = 0; e < n_events; ++e)
+        c->tile_h[e + 1] = c->tile_h[e] + (c->off_h[e + 1] - c->off_h[e] + kTile - 1) / kTile;
+    c->n_tiles = c->tile_h[n_events];
+    std::vector<uint32_t> tile_event(std::max<uint32_t>(c->n_tiles, 1), 0);
+    for (int32_t e = 0; e < n_events; ++e)
+        for (uint32_t t = c->tile_h[e]; t < c->tile_h[e + 1]; ++t) tile_event[t] = (uint32_t)e;
+    c->order_h.resize(n_events);
+    std::iota(c->order_h.begin(), c->order_h.end(), 0u);
+    std::stable_sort(c->order_h.begin(), c->order_h.end(), [&](uint32_t a, uint32_t b) {
+        return c->off_h[a + 1] - c->off_h[a] > c->off_h[b + 1] - c->off_h[b];
+    });
+    choose_chunks(c);
+
+    const size_t d = (size_t)n * sizeof(double);
+    const size_t E = (size_t)n_events;
+    bool ok = hipMalloc(&c->x, d) == hipSuccess && hipMalloc(&c->y, d) == hipSuccess &&
+              hipMalloc(&c->z, d) == hipSuccess &&
+              hipMalloc(&c->cstep, (size_t)n * sizeof(int32_t)) == hipSuccess &&
+              hipMalloc(&c->ev_of, (size_t)n * sizeof(uint32_t)) == hipSuccess &&
+              hipMalloc(&c->keys[0], (size_t)n * sizeof(uint64_t)) == hipSuccess &&
+              hipMalloc(&c->keys[1], (size_t)n * sizeof(uint64_t)) == hipSuccess &&
+              hipMalloc(&c->ps[0], d) == hipSuccess && hipMalloc(&c->ps[1], d) == hipSuccess &&
+              hipMalloc(&c->ps[2], d) == hipSuccess &&
+              hipMalloc(&c->tile_box, 6 * sizeof(double) * tile_event.size()) == hipSuccess &&
+              hipMalloc(&c->ev_off_d, (E + 1) * sizeof(uint32_t)) == hipSuccess &&
+              hipMalloc(&c->ev_tile_d, (E + 1) * sizeof(uint32_t)) == hipSuccess &&
+              hipMalloc(&c->tile_event_d, tile_event.size() * sizeof(uint32_t)) == hipSuccess &&
+              hipMalloc(&c->ev_active_d, E * sizeof(uint32_t)) == hipSuccess &&
+              hipMalloc(&c->ev_chunks_d, E * sizeof(int32_t)) == hipSuccess &&
+              hipHostMalloc((void**)&c->host_active, E * sizeof(uint32_t)) == hipSuccess;
+    if (!ok) {
         free_buffers(c);
-        const size_t d = (size_t)n * sizeof(double);
-        const size_t i = (size_t)n * sizeof(int32_t);
-        const size_t k = (size_t)n * sizeof(uint64_t);
-        bool ok = hipMalloc(&c->x, d) == hipSuccess && hipMalloc(&c->y, d) == hipSuccess &&
-                  hipMalloc(&c->z, d) == hipSuccess && hipMalloc(&c->cstep, i) == hipSuccess &&
-                  hipMalloc(&c->keys[0], k) == hipSuccess &&
-                  hipMalloc(&c->keys[1], k) == hipSuccess &&
-                  hipMalloc(&c->keys[2], k) == hipSuccess &&
-                  hipMalloc(&c->tile_box, 6 * sizeof(double) * (size_t)((n + kTile - 1) / kTile)) ==
-                      hipSuccess &&
-                  hipMalloc(&c->ps[0][0], d) == hipSuccess && hipMalloc(&c->ps[0][1], d) == hipSuccess &&
-                  hipMalloc(&c->ps[0][2], d) == hipSuccess && hipMalloc(&c->ps[1][0], d) == hipSuccess &&
-                  hipMalloc(&c->ps[1][1], d) == hipSuccess && hipMalloc(&c->ps[1][2], d) == hipSuccess &&
-                  hipMalloc(&c->part, (size_t)kMaxChunks * 3 * (size_t)n * sizeof(float)) ==
-                      hipSuccess;
-        if (!ok) {
-            free_buffers(c);
-            c->loaded = false;
-            return fail(c, GCCD_E_NOMEM, "gccd_load: device allocation failed");
-        }
-        c->cap = n;
-        c->tile_stride = (uint32_t)((n + kTile - 1) / kTile);
+        return fail(c, GCCD_E_NOMEM, "gccd_load_events: device allocation failed");
     }
     size_t need = 0;
-    GCCD_HIP(c, sort_keys_storage((uint32_t)n, kMortonBits + 1u + bits, &need));
-    if (need > c->sort_tmp_bytes) {
-        (void)hipFree(c->sort_tmp);
-        c->sort_tmp = nullptr;
-        c->sort_tmp_bytes = 0;
-        if (hipMalloc(&c->sort_tmp, need) != hipSuccess) {
-            free_buffers(c);
-            c->loaded = false;
-            return fail(c, GCCD_E_NOMEM, "gccd_load: sort storage allocation failed");
-        }
-        c->sort_tmp_bytes = need;
+    GCCD_HIP(c, sort_keys_storage((uint32_t)n, kl.lbits + kMortonBits + 1 + kl.ebits, &need));
+    if (hipMalloc(&c->sort_tmp, std::max<size_t>(need, 1)) != hipSuccess) {
+        free_buffers(c);
+        return fail(c, GCCD_E_NOMEM, "gccd_load_events: sort storage allocation failed");
     }
-    c->idx_bits = bits;
-    const size_t bytes = (size_t)n * sizeof(double);
-    GCCD_HIP(c, hipMemcpyAsync(c->x, x, bytes, hipMemcpyDeviceToDevice, c->stream));
-    GCCD_HIP(c, hipMemcpyAsync(c->y, y, bytes, hipMemcpyDeviceToDevice, c->stream));
-    GCCD_HIP(c, hipMemcpyAsync(c->z, z, bytes, hipMemcpyDeviceToDevice, c->stream));
+    c->sort_tmp_bytes = std::max<size_t>(need, 1);
+    GCCD_HIP(c, hipMemcpyAsync(c->ev_off_d, c->off_h.data(), (E + 1) * sizeof(uint32_t),
+                               hipMemcpyHostToDevice, c->stream));
+    GCCD_HIP(c, hipMemcpyAsync(c->ev_tile_d, c->tile_h.data(), (E + 1) * sizeof(uint32_t),
+                               hipMemcpyHostToDevice, c->stream));
+    GCCD_HIP(c, hipMemcpyAsync(c->tile_event_d, tile_event.data(),
+                               tile_event.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                               c->stream));
+    {
+        int r = size_chunk_buffers(c);  // synchronises: tile_event may go out of scope
+        if (r != GCCD_OK) {
+            free_buffers(c);
+            return r;
+        }
+    }
+
+    GCCD_HIP(c, hipMemcpyAsync(c->x, x, d, hipMemcpyDeviceToDevice, c->stream));
+    GCCD_HIP(c, hipMemcpyAsync(c->y, y, d, hipMemcpyDeviceToDevice, c->stream));
+    GCCD_HIP(c, hipMemcpyAsync(c->z, z, d, hipMemcpyDeviceToDevice, c->stream));
     GCCD_HIP(c, launch_fill_u32(c->meta, kMetaWords, 0u, c->stream));
-    c->full_list = c->p.coulomb && c->p.collected_are_sources;
-    if (!c->full_list) GCCD_HIP(c, launch_fill_u64(c->keys[1], (uint64_t)n, kNoKey, c->stream));
-    GCCD_HIP(c, launch_load(c->z, c->cstep, c->keys[1], c->meta + 0, c->x, c->y, (uint32_t)n,
-                            bits, c->full_list ? 1 : 0, c->p.thickness_um, c->p.well_z_um,
-                            c->stream));
-    GCCD_HIP(c, sort_keys(c->sort_tmp, c->sort_tmp_bytes, c->keys[1], c->keys[0], (uint32_t)n,
-                          kMortonBits + 1u + bits, c->stream));
+    GCCD_HIP(c, launch_load(c->z, c->cstep, c->ev_off_d, c->ev_of, c->n_events, (uint32_t)n,
+                            c->p.thickness_um, c->p.well_z_um, c->meta + kMetaCount, c->stream));
+    c->list_mode = c->p.coulomb != 0;
     c->cur = 0;
-    GCCD_HIP(c, hipMemcpyAsync(c->host_meta, c->meta, kMetaWords * sizeof(uint32_t),
-                               hipMemcpyDeviceToHost, c->stream));
-    GCCD_HIP(c, hipStreamSynchronize(c->stream));
-    c->n = n;
+    if (c->list_mode) {
+        GCCD_HIP(c, launch_make_keys(c->x, c->y, c->z, c->cstep, c->ev_of, c->ev_off_d,
+                                     (uint32_t)n, c->kl, c->keys[1], c->stream));
+        int r = finish_list(c);
+        if (r != GCCD_OK) return r;
+    }
+    {
+        int r = read_counts(c);
+        if (r != GCCD_OK) return r;
+    }
+    c->n_active = c->list_mode ? (int64_t)meta64(c, kMetaPending) : c->host_meta[kMetaCount];
     c->step = 0;
-    c->n_active = c->host_meta[0];
     c->loaded = true;
     c->field_ms = 0;
     c->field_launches = 0;
     c->ev_used = 0;
     return GCCD_OK;
+}
+
+int gccd_load(gccd_ctx* c, int64_t n, const double* x, const double* y, const double* z) {
+    if (!c) return GCCD_E_INVALID;
+    if (n <= 0 || n > (1ll << kMaxKeyPayload))
+        return fail(c, GCCD_E_INVALID, "gccd_load: n out of range");
+    const int64_t off[2] = {0, n};
+    return gccd_load_events(c, 1, off, x, y, z);
 }
 
 int gccd_set_launch(gccd_ctx* c, int32_t tpt, int32_t chunks) {
@@ -349,6 +541,16 @@ int gccd_set_launch(gccd_ctx* c, int32_t tpt, int32_t chunks) {
         return fail(c, GCCD_E_INVALID, "gccd_set_launch: shape out of range");
     c->tpt_fixed = tpt;
     c->chunks_fixed = chunks;
+    if (c->loaded) {
+        GCCD_HIP(c, hipStreamSynchronize(c->stream));
+        c->tpt = tpt ? tpt : 1;
+        choose_chunks(c);
+        int r = size_chunk_buffers(c);
+        if (r != GCCD_OK) {
+            free_buffers(c);
+            return r;
+        }
+    }
     return GCCD_OK;
 }
 
@@ -369,21 +571,30 @@ int gccd_run(gccd_ctx* c, double dt_ps, int64_t max_steps, int64_t* steps_done,
 
     const int64_t step0 = c->step;
     const uint32_t n = (uint32_t)c->n;
-    uint32_t bound = (uint32_t)c->n_active;
+    int64_t bound = c->n_active;
+    GCCD_HIP(c, hipStreamSynchronize(c->stream));  // the item staging buffer is free
+    if (c->list_mode && bound > 0) {
+        int r = build_items(c, c->host_active);
+        if (r != GCCD_OK) return r;
+    }
 
     StepArgs sa{};
     sa.x = c->x;
     sa.y = c->y;
     sa.z = c->z;
     sa.cstep = c->cstep;
+    sa.list_mode = c->list_mode ? 1 : 0;
+    sa.ev_off = c->ev_off_d;
+    sa.ev_active = c->ev_active_d;
+    sa.ev_chunks = c->ev_chunks_d;
+    sa.ev_of = c->ev_of;
+    sa.kl = c->kl;
     sa.part = c->part;
     sa.pstride = n;
+    sa.n_all = n;
     sa.coulomb = c->p.coulomb;
     sa.diffusion = c->p.diffusion;
     sa.mobility_model = c->p.mobility_model;
-    sa.src_all = c->p.collected_are_sources;
-    sa.n_all = n;
-    sa.idx_bits = c->idx_bits;
     sa.K = c->K;
     sa.a1 = c->p.a1_Vcm_per_um;
     sa.a2 = c->p.a2_Vcm;
@@ -395,98 +606,64 @@ int gccd_run(gccd_ctx* c, double dt_ps, int64_t max_steps, int64_t* steps_done,
     sa.inv_beta = c->inv_beta;
     sa.dt_s = dt_ps * 1e-12;
     sa.vt = c->vt;
-    sa.event = c->p.event;
+    sa.event0 = c->p.event;
     sa.key0 = (uint32_t)c->p.seed;
     sa.key1 = (uint32_t)(c->p.seed >> 32);
-    sa.stats = reinterpret_cast<unsigned long long*>(c->meta + 8);
-    sa.misc = reinterpret_cast<int32_t*>(c->meta + 3);
-
-    const uint64_t idx_mask = (1ull << c->idx_bits) - 1ull;
-    FieldArgs fa{};
-    fa.tx = fa.sx = c->ps[0][0];
-    fa.ty = fa.sy = c->ps[0][1];
-    fa.tz = fa.sz = c->ps[0][2];
-    fa.tile_box = c->tile_box;
-    fa.tile_stride = c->tile_stride;
-    fa.eps2 = (float)(c->p.softening_um * c->p.softening_um);
-    fa.part = c->part;
-    fa.pstride = n;
-    int tpt, chunks;
-    choose_shape(c, n, n, &tpt, &chunks);
-    const uint32_t end_bit = kMortonBits + 1u + c->idx_bits;
-    sa.full_list = c->full_list ? 1 : 0;
+    sa.pending = reinterpret_cast<const unsigned long long*>(c->meta + kMetaPending);
+    sa.stats = reinterpret_cast<unsigned long long*>(c->meta + kMetaStats);
+    sa.misc = reinterpret_cast<int32_t*>(c->meta + kMetaFlag);
 
     int64_t k = 0;
     while (k < max_steps && bound > 0) {
         const int64_t chunk_steps = (max_steps - k < kPoll) ? (max_steps - k) : kPoll;
         for (int64_t i = 0; i < chunk_steps; ++i) {
             const uint32_t s = (uint32_t)(step0 + k + i);
-            uint64_t* kin = c->keys[c->cur];
-            uint64_t* kout = c->keys[c->cur ^ 1];
-            uint32_t* cin = c->meta + (s % 3u);
-            if (c->p.coulomb) {
-                // targets: the travelling holes, first in the list; sources:
-                // the whole list (full) or the same travelling holes; both
-                // read from the slot-ordered copy gathered here
-                fa.tcount = cin;
-                fa.nt = bound;
-                fa.scount = c->full_list ? nullptr : cin;
-                fa.ns = c->full_list ? n : bound;
-                fa.nchunk = chunks;
-                c->last_tpt = tpt;
-                c->last_chunks = chunks;
-                GCCD_HIP(c, launch_gather(kin, fa.scount, fa.ns, fa.ns, idx_mask, n, c->x, c->y,
-                                          c->z, c->ps[0][0], c->ps[0][1], c->ps[0][2],
-                                          c->tile_box, c->tile_stride, c->stream));
+            sa.step = s;
+            if (c->list_mode) {
+                FieldArgs fa = field_args(c, false);
                 hipEvent_t* evp = nullptr;
                 int r = record_field_start(c, &evp);
                 if (r != GCCD_OK) return r;
-                GCCD_HIP(c, launch_field(fa, tpt, bound, c->stream));
+                GCCD_HIP(c, launch_field(fa, c->tpt, c->n_items, c->stream));
                 if (evp) GCCD_HIP(c, hipEventRecord(evp[1], c->stream));
-                sa.nchunk = chunks;
+                sa.keys_in = c->keys[c->cur];
+                sa.keys_out = c->keys[c->cur ^ 1];
+                GCCD_HIP(c, launch_step(sa, n, c->stream));
+                r = finish_list(c);  // next step's sorted list, counts, positions
+                if (r != GCCD_OK) return r;
             } else {
-                sa.nchunk = 0;
-            }
-            if (!c->full_list) GCCD_HIP(c, launch_fill_u64(kout, bound, kNoKey, c->stream));
-            sa.keys_in = kin;
-            sa.cnt_in = cin;
-            sa.keys_out = kout;
-            sa.cnt_out = c->meta + ((s + 1u) % 3u);
-            sa.cnt_clear = c->meta + ((s + 2u) % 3u);
-            sa.step = s;
-            GCCD_HIP(c, launch_step(sa, bound, c->stream));
-            if (c->p.coulomb) {
-                // next step's list in spatial order, travelling holes first
-                // (the unused tail of a travelling-only list holds kNoKey)
-                GCCD_HIP(c, sort_keys(c->sort_tmp, c->sort_tmp_bytes, kout, kin,
-                                      c->full_list ? n : bound, end_bit, c->stream));
-            } else {
-                c->cur ^= 1;
+                sa.cnt_in = c->meta + kMetaCount + (s % 3u);
+                sa.cnt_out = c->meta + kMetaCount + ((s + 1u) % 3u);
+                sa.cnt_clear = c->meta + kMetaCount + ((s + 2u) % 3u);
+                GCCD_HIP(c, launch_step(sa, n, c->stream));
             }
         }
         k += chunk_steps;
-        GCCD_HIP(c, hipMemcpyAsync(c->host_meta, c->meta, kMetaWords * sizeof(uint32_t),
-                                   hipMemcpyDeviceToHost, c->stream));
-        GCCD_HIP(c, hipStreamSynchronize(c->stream));
+        int r = read_counts(c);
+        if (r != GCCD_OK) return r;
         if (c->timing) {
-            int r = collect_timing(c);
+            r = collect_timing(c);
             if (r != GCCD_OK) return r;
         }
-        const uint32_t s_next = (uint32_t)(step0 + k);
-        bound = c->host_meta[s_next % 3u];
-        if (c->host_meta[3] != 0) {
-            // The active-list ring may now be ahead of the step counter: the
-            // state is unusable until the next gccd_load.
-            c->step = (int64_t)(uint32_t)c->host_meta[4];
+        if (c->list_mode)
+            bound = (int64_t)meta64(c, kMetaPending);
+        else
+            bound = c->host_meta[kMetaCount + (uint32_t)(step0 + k) % 3u];
+        if (c->host_meta[kMetaFlag] != 0) {
+            c->step = (int64_t)(uint32_t)c->host_meta[kMetaLast];
             c->n_active = bound;
             c->loaded = false;
             return fail(c, GCCD_E_NONFINITE,
                         "gccd_run: a carrier position became non-finite; reload to continue");
         }
+        if (c->list_mode && bound > 0 && k < max_steps) {
+            r = build_items(c, c->host_active);  // counts only shrink: fewer items
+            if (r != GCCD_OK) return r;
+        }
     }
     // The step after the last one that moved a hole: later steps found no hole
-    // travelling and left the state (and the counter ring, all zero) unchanged.
-    const int64_t last = (k > 0) ? (int64_t)(uint32_t)c->host_meta[4] : step0;
+    // travelling and left the state unchanged.
+    const int64_t last = (k > 0) ? (int64_t)(uint32_t)c->host_meta[kMetaLast] : step0;
     c->step = (last > step0) ? last : step0;
     c->n_active = bound;
     if (steps_done) *steps_done = c->step - step0;
@@ -499,70 +676,23 @@ int gccd_field(gccd_ctx* c, double* ex, double* ey, double* ez) {
     if (!c->loaded) return fail(c, GCCD_E_STATE, "gccd_field before gccd_load");
     if (!ex || !ey || !ez) return fail(c, GCCD_E_INVALID, "gccd_field: NULL pointer");
     const uint32_t n = (uint32_t)c->n;
-    const uint32_t s = (uint32_t)c->step;
-    const uint32_t end_bit = kMortonBits + 1u + c->idx_bits;
-    const uint64_t idx_mask = (1ull << c->idx_bits) - 1ull;
-    FieldArgs fa{};
-    fa.tile_box = c->tile_box;
-    fa.tile_stride = c->tile_stride;
-    fa.eps2 = (float)(c->p.softening_um * c->p.softening_um);
-    fa.part = c->part;
-    fa.pstride = n;
-    fa.nt = n;
-    fa.tcount = nullptr;
-    fa.sx = c->ps[0][0];
-    fa.sy = c->ps[0][1];
-    fa.sz = c->ps[0][2];
-    const uint64_t* tkeys = nullptr;
-    if (c->full_list || c->p.collected_are_sources) {
-        // every carrier is both a target and a source: the run's list when it
-        // holds all of them, else all keys sorted into the unused list
-        const uint64_t* all = c->keys[c->cur];
-        if (!c->full_list) {
-            uint64_t* tk = c->keys[c->cur ^ 1];
-            GCCD_HIP(c, launch_keys_all(c->x, c->y, c->z, n, c->idx_bits, c->keys[2], c->stream));
-            GCCD_HIP(c, sort_keys(c->sort_tmp, c->sort_tmp_bytes, c->keys[2], tk, n, end_bit,
-                                  c->stream));
-            all = tk;
-        }
-        GCCD_HIP(c, launch_gather(all, nullptr, n, n, idx_mask, n, c->x, c->y, c->z, c->ps[0][0],
-                                  c->ps[0][1], c->ps[0][2], c->tile_box, c->tile_stride,
-                                  c->stream));
-        fa.tx = c->ps[0][0];
-        fa.ty = c->ps[0][1];
-        fa.tz = c->ps[0][2];
-        fa.scount = nullptr;
-        fa.ns = n;
-        tkeys = all;
-    } else {
-        // sources: the travelling holes (the run's list); targets: every
-        // carrier, sorted into the unused list
-        uint32_t* cnt = c->meta + (s % 3u);
-        const uint32_t na = (uint32_t)c->n_active;
-        GCCD_HIP(c, launch_gather(c->keys[c->cur], cnt, na, na, idx_mask, n, c->x, c->y, c->z,
-                                  c->ps[0][0], c->ps[0][1], c->ps[0][2], c->tile_box,
-                                  c->tile_stride, c->stream));
-        uint64_t* tk = c->keys[c->cur ^ 1];
-        GCCD_HIP(c, launch_keys_all(c->x, c->y, c->z, n, c->idx_bits, c->keys[2], c->stream));
-        GCCD_HIP(c, sort_keys(c->sort_tmp, c->sort_tmp_bytes, c->keys[2], tk, n, end_bit,
-                              c->stream));
-        GCCD_HIP(c, launch_gather(tk, nullptr, n, n, idx_mask, n, c->x, c->y, c->z, c->ps[1][0],
-                                  c->ps[1][1], c->ps[1][2], nullptr, 0, c->stream));
-        fa.tx = c->ps[1][0];
-        fa.ty = c->ps[1][1];
-        fa.tz = c->ps[1][2];
-        fa.scount = cnt;
-        fa.ns = na;
-        tkeys = tk;
+    GCCD_HIP(c, hipStreamSynchronize(c->stream));  // the item staging buffer is free
+    if (!c->list_mode) {
+        // no list is kept without Coulomb repulsion: build one for this call
+        GCCD_HIP(c, launch_make_keys(c->x, c->y, c->z, c->cstep, c->ev_of, c->ev_off_d, n, c->kl,
+                                     c->keys[c->cur ^ 1], c->stream));
+        int r = finish_list(c);
+        if (r != GCCD_OK) return r;
     }
-    int tpt, chunks;
-    choose_shape(c, n, n, &tpt, &chunks);
-    fa.nchunk = chunks;
-    c->last_tpt = tpt;
-    c->last_chunks = chunks;
-    GCCD_HIP(c, launch_field(fa, tpt, n, c->stream));
-    GCCD_HIP(c, launch_field_finish(c->part, n, chunks, tkeys, idx_mask, n, c->K, ex, ey, ez,
-                                    c->stream));
+    std::vector<uint32_t> all(c->n_events);
+    for (uint32_t e = 0; e < c->n_events; ++e) all[e] = c->off_h[e + 1] - c->off_h[e];
+    int r = build_items(c, all.data());
+    if (r != GCCD_OK) return r;
+    FieldArgs fa = field_args(c, true);
+    GCCD_HIP(c, launch_field(fa, c->tpt, c->n_items, c->stream));
+    GCCD_HIP(c, launch_field_finish(c->part, n, c->ev_chunks_d, c->keys[c->cur], c->ev_off_d,
+                                    c->kl, n, c->K, ex, ey, ez, c->stream));
+    GCCD_HIP(c, hipStreamSynchronize(c->stream));  // host_items may be rebuilt next
     return GCCD_OK;
 }
 
@@ -579,38 +709,50 @@ int gccd_positions(gccd_ctx* c, double* x, double* y, double* z, int32_t* collec
     return GCCD_OK;
 }
 
-int gccd_image(gccd_ctx* c, double x0, double y0, double pitch, int32_t nx, int32_t ny,
-               uint32_t* counts, uint64_t* n_outside) {
+static int image_common(gccd_ctx* c, double x0, double y0, double pitch, int32_t nx, int32_t ny,
+                        uint32_t* counts, uint64_t* n_outside, bool per_event) {
     if (!c) return GCCD_E_INVALID;
-    if (!is_finite(x0) || !is_finite(y0) || !is_finite(pitch) || !(pitch > 0) || nx <= 0 || ny <= 0 ||
-        (int64_t)nx * (int64_t)ny > 2147483648LL || !counts || !n_outside)
+    if (!is_finite(x0) || !is_finite(y0) || !is_finite(pitch) || !(pitch > 0) || nx <= 0 ||
+        ny <= 0 || (int64_t)nx * (int64_t)ny > 2147483648LL || !counts || !n_outside)
         return fail(c, GCCD_E_INVALID, "gccd_image: bad grid or NULL pointer");
     if (!c->loaded) return fail(c, GCCD_E_STATE, "gccd_image before gccd_load");
-    GCCD_HIP(c, launch_fill_u32(counts, (uint64_t)nx * (uint64_t)ny, 0u, c->stream));
-    GCCD_HIP(c, launch_fill_u32(reinterpret_cast<uint32_t*>(n_outside), 2, 0u, c->stream));
-    GCCD_HIP(c, launch_image(c->x, c->y, c->cstep, (uint32_t)c->n, x0, y0, pitch, nx, ny, counts,
+    const uint64_t grids = per_event ? c->n_events : 1;
+    GCCD_HIP(c, launch_fill_u32(counts, grids * (uint64_t)nx * (uint64_t)ny, 0u, c->stream));
+    GCCD_HIP(c, launch_fill_u32(reinterpret_cast<uint32_t*>(n_outside), 2 * grids, 0u, c->stream));
+    GCCD_HIP(c, launch_image(c->x, c->y, c->cstep, c->ev_of, (uint32_t)c->n, per_event ? 1 : 0,
+                             x0, y0, pitch, nx, ny, counts,
                              reinterpret_cast<unsigned long long*>(n_outside), c->stream));
     return GCCD_OK;
+}
+
+int gccd_image(gccd_ctx* c, double x0, double y0, double pitch, int32_t nx, int32_t ny,
+               uint32_t* counts, uint64_t* n_outside) {
+    return image_common(c, x0, y0, pitch, nx, ny, counts, n_outside, false);
+}
+
+int gccd_image_events(gccd_ctx* c, double x0, double y0, double pitch, int32_t nx, int32_t ny,
+                      uint32_t* counts, uint64_t* n_outside) {
+    return image_common(c, x0, y0, pitch, nx, ny, counts, n_outside, true);
 }
 
 int gccd_stats(gccd_ctx* c, gccd_stats_t* out) {
     if (!c || !out) return GCCD_E_INVALID;
     memset(out, 0, sizeof *out);
-    out->targets_per_thread = c->last_tpt;
-    out->source_chunks = c->last_chunks;
+    out->targets_per_thread = c->tpt;
+    out->source_chunks = c->loaded ? c->chunks_h[0] : 0;
     out->field_ms = c->field_ms;
     out->field_launches = c->field_launches;
     if (!c->loaded) return GCCD_OK;
     GCCD_HIP(c, hipMemcpyAsync(c->host_meta, c->meta, kMetaWords * sizeof(uint32_t),
                                hipMemcpyDeviceToHost, c->stream));
     GCCD_HIP(c, hipStreamSynchronize(c->stream));
-    uint64_t st[2];
-    memcpy(st, c->host_meta + 8, sizeof st);
     out->step = c->step;
     out->n_carriers = c->n;
     out->n_active = c->n_active;
-    out->carrier_steps = st[0];
-    out->pair_interactions = st[1];
+    out->carrier_steps = meta64(c, kMetaStats);
+    out->pair_interactions = meta64(c, kMetaStats + 2);
+    out->n_events = c->n_events;
+    out->max_source_chunks = c->max_chunks;
     return GCCD_OK;
 }
 

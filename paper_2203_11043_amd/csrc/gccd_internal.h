@@ -11,34 +11,45 @@ constexpr int kTile = 256;           // sources staged in LDS per tile
 constexpr int kMaxChunks = 64;       // largest source split of one target's sum
 constexpr int kStepThreads = 256;
 
-// Carrier lists hold 64-bit keys: the carrier index in the low idx_bits
-// bits, a 36-bit Morton code of the hole's 0.25 um cell above it, and above
-// that a bit set for collected holes.  Keys are unique, so sorting them is
-// deterministic; the sorted order puts travelling holes first and groups
-// nearby holes into the same workgroup and the same source tile.
+// Carrier lists hold one 64-bit key per carrier:
+//   [event | collected | 36-bit Morton code of the 0.25 um cell | local index]
+// with the local index (within its event) in the low lbits bits and the
+// event in the top ebits bits (ebits + lbits <= 27).  Keys are unique, so
+// sorting them is deterministic; the sorted list is one segment per event,
+// in event order, each holding its travelling holes first and each part in
+// spatial order, so nearby holes share workgroups and source tiles.
 constexpr double kCellPerUm = 4.0;     // Morton cells of 0.25 um
 constexpr int kMortonBits = 36;        // 12 bits per axis (wraps every 1024 um)
-constexpr uint64_t kNoKey = ~0ull;     // sorts after every real key
+constexpr int kMaxKeyPayload = 27;     // ebits + lbits
 
-// Targets and sources of one Eq. (6) launch, as FP64 positions already laid
-// out in list-slot order (gathered from the carrier arrays after each sort),
-// so that every read of the field kernel is coalesced.
+struct KeyLayout {
+    uint32_t lbits;   // local index bits
+    uint32_t ebits;   // event bits
+};
+
+// One workgroup of the Eq. (6) launch: targets [blk * 256 * TPT, ...) of the
+// event's target slots, against the source tiles chunk, chunk + nchunk, ...
+struct FieldItem {
+    uint32_t event;
+    uint32_t blk;
+    uint32_t chunk;
+    uint32_t nchunk;
+};
+
 struct FieldArgs {
-    const double* tx;
-    const double* ty;
-    const double* tz;
-    const uint32_t* tcount;   // device count of targets; NULL: use nt
-    uint32_t nt;
-    const double* sx;
-    const double* sy;
-    const double* sz;
-    const uint32_t* scount;   // device count of sources; NULL: use ns
-    uint32_t ns;
-    const double* tile_box;   // [6][tile_stride] boxes of the source tiles, or NULL
+    const FieldItem* items;
+    const uint32_t* ev_off;     // [E+1] first slot (and carrier) of each event
+    const uint32_t* ev_active;  // [E] travelling holes of each event (first in its segment)
+    const uint32_t* ev_tile;    // [E+1] first source tile of each event
+    int32_t targets_all;        // 1: every carrier of the event is a target
+    int32_t sources_all;        // 1: every carrier is a source, else the travelling ones
+    const double* px;           // positions in list-slot order (gathered)
+    const double* py;
+    const double* pz;
+    const double* tile_box;     // [6][tile_stride] boxes of the source tiles
     uint32_t tile_stride;
-    int32_t nchunk;           // source chunks (partials per target)
-    float eps2;               // softening length squared, um^2
-    float* part;              // [nchunk][3][pstride] FP32 partial sums
+    float eps2;                 // softening length squared, um^2
+    float* part;                // [chunk][3][pstride] FP32 partial sums by slot
     uint32_t pstride;
 };
 
@@ -48,21 +59,20 @@ struct StepArgs {
     double* y;
     double* z;
     int32_t* cstep;
-    const uint64_t* keys_in;  // this step's list; its first *cnt_in keys travel
-    const uint32_t* cnt_in;
-    uint64_t* keys_out;       // next step's list, before sorting
-    int32_t full_list;        // 1: lists hold all n carriers, else travelling ones only
-    uint32_t* cnt_out;
-    uint32_t* cnt_clear;
+    int32_t list_mode;         // 1: slots of the sorted list (Coulomb on); 0: carriers
+    const uint64_t* keys_in;   // this step's sorted list (list mode)
+    uint64_t* keys_out;        // next step's list, before sorting (list mode)
+    const uint32_t* ev_off;    // [E+1]
+    const uint32_t* ev_active; // [E] (list mode)
+    const int32_t* ev_chunks;  // [E] chunks of each event's field sum (list mode)
+    const uint32_t* ev_of;     // [n] event of each carrier (carrier mode)
+    KeyLayout kl;
     const float* part;
     uint32_t pstride;
-    int32_t nchunk;
+    uint32_t n_all;
     int32_t coulomb;
     int32_t diffusion;
     int32_t mobility_model;
-    int32_t src_all;          // 1: sources are all n carriers
-    uint32_t n_all;
-    uint32_t idx_bits;        // low key bits holding the carrier index
     double K;                 // V um^2 / cm
     double a1, a2;            // Eq. (1)
     double thickness, z_well;
@@ -70,34 +80,41 @@ struct StepArgs {
     double dt_s;              // time step, s
     double vt;                // k_B T / q, V
     uint32_t step;
-    uint32_t event;
+    uint32_t event0;          // Philox event word of event 0
     uint32_t key0, key1;
+    const uint32_t* cnt_in;   // carrier mode: travelling holes at the start of the step
+    uint32_t* cnt_out;        // carrier mode: ... of the next step (zeroed beforehand)
+    uint32_t* cnt_clear;      // carrier mode: counter of the step after next
+    const unsigned long long* pending;  // list mode: [0] holes, [1] pairs of this step
     unsigned long long* stats;  // [0] carrier-steps, [1] pair interactions
     int32_t* misc;              // [0] non-finite flag, [1] step after the last busy one
 };
 
-hipError_t launch_field(const FieldArgs& a, int tpt, uint32_t nt_bound, hipStream_t s);
-hipError_t launch_step(const StepArgs& a, uint32_t n_bound, hipStream_t s);
-hipError_t launch_load(double* z, int32_t* cstep, uint64_t* keys, uint32_t* cnt,
-                       const double* x, const double* y, uint32_t n, uint32_t idx_bits,
-                       int full_list, double thickness, double z_well, hipStream_t s);
-// Gathers the positions of the first *count (or count_c) keys of a list into
-// slot order and, if box is not NULL, the bounding box of every tile of kTile
-// slots.
-hipError_t launch_gather(const uint64_t* keys, const uint32_t* count, uint32_t count_c,
-                         uint32_t bound, uint64_t idx_mask, uint32_t n_all, const double* x,
-                         const double* y, const double* z, double* px, double* py, double* pz,
-                         double* box, uint32_t stride, hipStream_t s);
-hipError_t launch_keys_all(const double* x, const double* y, const double* z, uint32_t n,
-                           uint32_t idx_bits, uint64_t* keys, hipStream_t s);
+hipError_t launch_field(const FieldArgs& a, int tpt, uint32_t n_items, hipStream_t s);
+hipError_t launch_step(const StepArgs& a, uint32_t n_slots, hipStream_t s);
+hipError_t launch_load(double* z, int32_t* cstep, const uint32_t* ev_off, uint32_t* ev_of,
+                       uint32_t n_events, uint32_t n, double thickness, double z_well,
+                       uint32_t* cnt, hipStream_t s);
+hipError_t launch_make_keys(const double* x, const double* y, const double* z,
+                            const int32_t* cstep, const uint32_t* ev_of, const uint32_t* ev_off,
+                            uint32_t n, KeyLayout kl, uint64_t* keys, hipStream_t s);
+hipError_t launch_gather(const uint64_t* keys, const uint32_t* ev_off, const uint32_t* ev_tile,
+                         const uint32_t* tile_event, const uint32_t* ev_active, int sources_all,
+                         uint32_t n_tiles, KeyLayout kl, const double* x, const double* y,
+                         const double* z, double* px, double* py, double* pz, double* box,
+                         uint32_t stride, hipStream_t s);
+hipError_t launch_count(const uint64_t* keys, const uint32_t* ev_off, uint32_t n_events,
+                        KeyLayout kl, int sources_all, uint32_t* ev_active,
+                        unsigned long long* pending, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
-hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
-hipError_t launch_field_finish(const float* part, uint32_t pstride, int nchunk,
-                               const uint64_t* tkeys, uint64_t idx_mask, uint32_t n, double K,
-                               double* ex, double* ey, double* ez, hipStream_t s);
-hipError_t launch_image(const double* x, const double* y, const int32_t* cstep, uint32_t n,
-                        double x0, double y0, double pitch, int32_t nx, int32_t ny,
-                        uint32_t* counts, unsigned long long* n_out, hipStream_t s);
+hipError_t launch_field_finish(const float* part, uint32_t pstride, const int32_t* ev_chunks,
+                               const uint64_t* keys, const uint32_t* ev_off, KeyLayout kl,
+                               uint32_t n, double K, double* ex, double* ey, double* ez,
+                               hipStream_t s);
+hipError_t launch_image(const double* x, const double* y, const int32_t* cstep,
+                        const uint32_t* ev_of, uint32_t n, int per_event, double x0, double y0,
+                        double pitch, int32_t nx, int32_t ny, uint32_t* counts,
+                        unsigned long long* n_out, hipStream_t s);
 
 // Sorting of key lists (rocPRIM radix sort; storage provided by the caller).
 hipError_t sort_keys_storage(uint32_t n, uint32_t end_bit, size_t* bytes);

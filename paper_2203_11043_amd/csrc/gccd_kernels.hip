@@ -2,8 +2,11 @@
 // Avalos & Sofo Haro, arXiv 2203.11043:
 //   field_tiles   -- Eq. (6), softened all-pairs Coulomb field (the O(N^2) part)
 //   step_update   -- Eqs. (1)-(4) and the z check of Sec. III.B, fused per carrier
-//   load_prepare  -- load-time boundary handling and first active list
+//   load_prepare  -- load-time boundary handling
+//   make_keys, count_active, gather_tiles -- the spatially sorted carrier list
 //   image_bin     -- 2D histogram of collected holes (Sec. V.A)
+// Several independent events (clouds) can share one launch; every kernel
+// keeps them apart through the per-event slot offsets.
 #include "gccd_internal.h"
 
 #include <math.h>
@@ -11,10 +14,8 @@
 namespace gccd {
 
 // ---------------------------------------------------------------------------
-// Spatial keys.  A hole's 0.25 um cell (12 bits per axis, wrapping every
-// 1024 um) is interleaved bit by bit into a 36-bit Morton code, placed above
-// the carrier index; one more bit above the code marks a collected hole, so a
-// sorted list holds the travelling holes first, each part in spatial order.
+// Keys.  A hole's 0.25 um cell (12 bits per axis, wrapping every 1024 um) is
+// interleaved bit by bit into a 36-bit Morton code.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t cell12(double v) {
     if (!isfinite(v)) return 0u;
@@ -32,22 +33,77 @@ __device__ __forceinline__ uint64_t morton36(uint32_t cx, uint32_t cy, uint32_t 
     return m;
 }
 
-__device__ __forceinline__ uint64_t spatial_key(double x, double y, double z, uint32_t j,
-                                                uint32_t idx_bits, bool collected) {
-    const uint64_t flag = collected ? (1ull << (kMortonBits + idx_bits)) : 0ull;
-    return flag | (morton36(cell12(x), cell12(y), cell12(z)) << idx_bits) | (uint64_t)j;
+__device__ __forceinline__ uint64_t make_key(uint32_t event, bool collected, double x, double y,
+                                             double z, uint32_t local, KeyLayout kl) {
+    uint64_t k = (uint64_t)local;
+    k |= morton36(cell12(x), cell12(y), cell12(z)) << kl.lbits;
+    if (collected) k |= 1ull << (kl.lbits + kMortonBits);
+    k |= (uint64_t)event << (kl.lbits + kMortonBits + 1);
+    return k;
+}
+
+__device__ __forceinline__ uint32_t key_local(uint64_t k, KeyLayout kl) {
+    return (uint32_t)(k & ((1ull << kl.lbits) - 1ull));
+}
+
+__device__ __forceinline__ uint32_t key_event(uint64_t k, KeyLayout kl) {
+    return (uint32_t)(k >> (kl.lbits + kMortonBits + 1));
+}
+
+__device__ __forceinline__ bool key_collected(uint64_t k, KeyLayout kl) {
+    return ((k >> (kl.lbits + kMortonBits)) & 1ull) != 0ull;
+}
+
+// event of carrier i: the last e with ev_off[e] <= i (binary search)
+__device__ __forceinline__ uint32_t event_of(const uint32_t* ev_off, uint32_t n_events,
+                                             uint32_t i) {
+    uint32_t lo = 0, hi = n_events;  // invariant: ev_off[lo] <= i < ev_off[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (ev_off[mid] <= i)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// A value every lane of the wave holds identically, moved to scalar
+// registers (the compiler cannot prove uniformity after a shuffle reduction).
+__device__ __forceinline__ double uniform(double v) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__device__ __forceinline__ float uniform(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = fmin(v, __shfl_xor(v, m));
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m));
+    return v;
 }
 
 // ---------------------------------------------------------------------------
-// Eq. (6):  E_j = K sum_i r_ij / (|r_ij|^2 + eps^2)^{3/2},  r_ij = r_j - r_i.
+// Eq. (6):  E_j = K sum_i r_ij / (|r_ij|^2 + eps^2)^{3/2},  r_ij = r_j - r_i,
+// summed over the sources of the target's own event.
 //
-// One workgroup owns kFieldThreads*TPT consecutive target slots of the
-// spatially sorted list (a compact region of the cloud) and one chunk of the
-// sources.  Sources are staged through LDS in tiles of kTile (double
-// buffered: the next tile's global loads are in flight while the current one
-// is consumed); every lane of every wave reads the same LDS words, so the
-// reads are bank-conflict-free broadcasts.  Each lane keeps TPT targets in
-// registers for independent dependency chains.
+// One workgroup takes one work item: kFieldThreads*TPT consecutive target
+// slots of one event's spatially sorted segment (a compact region of the
+// cloud) and one chunk of that event's source tiles.  Sources are staged
+// through LDS in tiles of kTile (double buffered: the next tile's global
+// loads are in flight while the current one is consumed); every lane of
+// every wave reads the same LDS words, so the reads are bank-conflict-free
+// broadcasts.  Each lane keeps TPT targets in registers.
 //
 // Precision.  The workgroup takes the centre o of its targets' bounding box
 // (half-diagonal rho) as origin and holds every coordinate, targets and
@@ -148,50 +204,30 @@ __device__ __forceinline__ void tile_terms(const float* __restrict__ hxp,
     }
 }
 
-// A value every lane of the wave holds identically, moved to scalar
-// registers (the compiler cannot prove uniformity after a shuffle reduction).
-__device__ __forceinline__ double uniform(double v) {
-    const uint64_t b = (uint64_t)__double_as_longlong(v);
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
-    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
-
-__device__ __forceinline__ float uniform(float v) {
-    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
-}
-
-__device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v = fmin(v, __shfl_xor(v, m));
-    return v;
-}
-
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m));
-    return v;
-}
-
 template <int TPT>
 __global__ __launch_bounds__(kFieldThreads) void field_tiles(FieldArgs a) {
     __shared__ __align__(16) float sh[2][6][kTile];
     __shared__ double box[6][kFieldThreads / 64];
     __shared__ double tbox[2][6];  // bounding box of the staged source tile
 
-    const uint32_t nt = a.tcount ? *a.tcount : a.nt;
-    const uint32_t ns = a.scount ? *a.scount : a.ns;
-    const int chunk = (int)(blockIdx.x % (uint32_t)a.nchunk);
-    const uint32_t tbase = (blockIdx.x / (uint32_t)a.nchunk) * (uint32_t)(kFieldThreads * TPT);
+    const FieldItem it = a.items[blockIdx.x];
+    const uint32_t off = a.ev_off[it.event];
+    const uint32_t ne = a.ev_off[it.event + 1] - off;
+    const uint32_t na = a.ev_active[it.event];
+    const uint32_t nt = a.targets_all ? ne : na;
+    const uint32_t ns = a.sources_all ? ne : na;
+    const uint32_t tbase = it.blk * (uint32_t)(kFieldThreads * TPT);
     if (tbase >= nt) return;  // the whole workgroup leaves before any barrier
 
-    // Chunk c takes the source tiles c, c + S, c + 2S, ... of the T tiles of
-    // kTile slots.  Each tile is a compact region (the list is spatially
-    // sorted) whose bounding box is precomputed; dealing them round-robin
-    // gives every chunk a sample of the whole cloud, so the close pairs --
-    // the costlier ones -- spread evenly over the workgroups.
+    // The item takes the event's source tiles chunk, chunk + S, chunk + 2S,
+    // ... of its T tiles.  Each tile is a compact region (the segment is
+    // spatially sorted) whose bounding box is precomputed; dealing them
+    // round-robin gives every chunk a sample of the whole cloud, so the
+    // close pairs -- the costlier ones -- spread evenly over the workgroups.
     const uint32_t ntiles = (ns + kTile - 1) / kTile;
-    const uint32_t step_t = (uint32_t)a.nchunk;
+    const uint32_t tile0 = a.ev_tile[it.event];
+    const uint32_t chunk = it.chunk;
+    const uint32_t step_t = it.nchunk;
     const int tid = threadIdx.x;
 
     // targets and their bounding box
@@ -200,12 +236,12 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles(FieldArgs a) {
     double hi_x = -INFINITY, hi_y = -INFINITY, hi_z = -INFINITY;
 #pragma unroll
     for (int t = 0; t < TPT; ++t) {
-        const uint32_t slot = tbase + (uint32_t)(t * kFieldThreads + tid);
+        const uint32_t ts = tbase + (uint32_t)(t * kFieldThreads + tid);
         px[t] = py[t] = pz[t] = 0.0;
-        if (slot < nt) {
-            px[t] = a.tx[slot];
-            py[t] = a.ty[slot];
-            pz[t] = a.tz[slot];
+        if (ts < nt) {
+            px[t] = a.px[off + ts];
+            py[t] = a.py[off + ts];
+            pz[t] = a.pz[off + ts];
             lo_x = fmin(lo_x, px[t]);
             lo_y = fmin(lo_y, py[t]);
             lo_z = fmin(lo_z, pz[t]);
@@ -278,11 +314,11 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles(FieldArgs a) {
         qy = oy;
         qz = oz;
         if (i < ns) {
-            qx = a.sx[i];
-            qy = a.sy[i];
-            qz = a.sz[i];
+            qx = a.px[off + i];
+            qy = a.py[off + i];
+            qz = a.pz[off + i];
         }
-        if (a.tile_box && tid < 6) qb = a.tile_box[(size_t)tid * a.tile_stride + t];
+        if (tid < 6) qb = a.tile_box[(size_t)tid * a.tile_stride + tile0 + t];
     };
     auto stage = [&](int b) {
         if (tid < 6) tbox[b][tid] = qb;
@@ -297,19 +333,19 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles(FieldArgs a) {
     };
 
     int buf = 0;
-    if ((uint32_t)chunk < ntiles) {
-        fetch((uint32_t)chunk);
+    if (chunk < ntiles) {
+        fetch(chunk);
         stage(0);
     }
     __syncthreads();
-    for (uint32_t t = (uint32_t)chunk; t < ntiles; t += step_t) {
+    for (uint32_t t = chunk; t < ntiles; t += step_t) {
         const uint32_t next = t + step_t;
         if (next < ntiles) fetch(next);
         const uint32_t cnt = min((uint32_t)kTile, ns - t * kTile);
 
         float bx[TPT], by[TPT], bz[TPT];
 #pragma unroll
-        for (int t = 0; t < TPT; ++t) bx[t] = by[t] = bz[t] = 0.0f;
+        for (int u = 0; u < TPT; ++u) bx[u] = by[u] = bz[u] = 0.0f;
 
         const float* hxp = sh[buf][0];
         const float* hyp = sh[buf][1];
@@ -319,14 +355,11 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles(FieldArgs a) {
         const float* lzp = sh[buf][5];
         // A tile whose bounding box is at least rho/4 from the targets' box
         // cannot hold a close pair: its pairs skip the per-pair check.
-        bool far_tile = false;
-        if (a.tile_box) {
-            const double* tb = tbox[buf];
-            const double gx = fmax(0.0, fmax(tb[0] - hi_x, lo_x - tb[3]));
-            const double gy = fmax(0.0, fmax(tb[1] - hi_y, lo_y - tb[4]));
-            const double gz = fmax(0.0, fmax(tb[2] - hi_z, lo_z - tb[5]));
-            far_tile = gx * gx + gy * gy + gz * gz >= rc2d;
-        }
+        const double* tb = tbox[buf];
+        const double gx = fmax(0.0, fmax(tb[0] - hi_x, lo_x - tb[3]));
+        const double gy = fmax(0.0, fmax(tb[1] - hi_y, lo_y - tb[4]));
+        const double gz = fmax(0.0, fmax(tb[2] - hi_z, lo_z - tb[5]));
+        const bool far_tile = gx * gx + gy * gy + gz * gz >= rc2d;
         if (far_tile) {
             tile_terms<TPT, false>(hxp, hyp, hzp, lxp, lyp, lzp, cnt, thx, thy, thz, tlx, tly, tlz,
                                    a.eps2, rc2, bx, by, bz);
@@ -335,55 +368,133 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles(FieldArgs a) {
                                   a.eps2, rc2, bx, by, bz);
         }
 #pragma unroll
-        for (int t = 0; t < TPT; ++t) {
-            ax[t] += bx[t];
-            ay[t] += by[t];
-            az[t] += bz[t];
+        for (int u = 0; u < TPT; ++u) {
+            ax[u] += bx[u];
+            ay[u] += by[u];
+            az[u] += bz[u];
         }
         if (next < ntiles) stage(buf ^ 1);
         __syncthreads();
         buf ^= 1;
     }
 
-    float* outx = a.part + (size_t)(chunk * 3 + 0) * a.pstride;
-    float* outy = a.part + (size_t)(chunk * 3 + 1) * a.pstride;
-    float* outz = a.part + (size_t)(chunk * 3 + 2) * a.pstride;
+    float* outx = a.part + (size_t)(chunk * 3 + 0) * a.pstride + off;
+    float* outy = a.part + (size_t)(chunk * 3 + 1) * a.pstride + off;
+    float* outz = a.part + (size_t)(chunk * 3 + 2) * a.pstride + off;
 #pragma unroll
     for (int t = 0; t < TPT; ++t) {
-        const uint32_t slot = tbase + (uint32_t)(t * kFieldThreads + tid);
-        if (slot < nt) {
-            outx[slot] = ax[t];
-            outy[slot] = ay[t];
-            outz[slot] = az[t];
+        const uint32_t ts = tbase + (uint32_t)(t * kFieldThreads + tid);
+        if (ts < nt) {
+            outx[ts] = ax[t];
+            outy[ts] = ay[t];
+            outz[ts] = az[t];
         }
     }
 }
 
-// Positions of a key list gathered into slot order, and the bounding box
-// (FP64, absolute coordinates) of each tile of kTile consecutive slots:
-// box[k * stride + tile], k = lo x, y, z, hi x, y, z.  One workgroup per tile.
-__global__ __launch_bounds__(kTile) void gather_tiles(const uint64_t* keys, const uint32_t* count,
-                                                      uint32_t count_c, uint64_t idx_mask,
-                                                      uint32_t n_all, const double* x,
-                                                      const double* y, const double* z,
-                                                      double* px, double* py, double* pz,
-                                                      double* box, uint32_t stride) {
+hipError_t launch_field(const FieldArgs& a, int tpt, uint32_t n_items, hipStream_t s) {
+    if (n_items == 0) return hipSuccess;
+    switch (tpt) {
+        case 1: field_tiles<1><<<n_items, kFieldThreads, 0, s>>>(a); break;
+        case 2: field_tiles<2><<<n_items, kFieldThreads, 0, s>>>(a); break;
+        case 4: field_tiles<4><<<n_items, kFieldThreads, 0, s>>>(a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+static uint32_t grid_for(uint64_t n, int threads, uint32_t cap) {
+    uint64_t g = (n + (uint64_t)threads - 1) / (uint64_t)threads;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (uint32_t)g;
+}
+
+// ---------------------------------------------------------------------------
+// The sorted list.  make_keys writes every carrier's key (carrier order);
+// after the sort, count_active finds in each event's segment the first
+// collected key (the segment holds its travelling holes first) and records
+// the step's holes and pair interactions; gather_tiles copies the positions
+// into slot order and takes the bounding box of every source tile.
+// ---------------------------------------------------------------------------
+__global__ void make_keys(const double* x, const double* y, const double* z,
+                          const int32_t* cstep, const uint32_t* ev_of, const uint32_t* ev_off,
+                          uint32_t n, KeyLayout kl, uint64_t* keys) {
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+        const uint32_t e = ev_of[j];
+        keys[j] = make_key(e, cstep[j] >= 0, x[j], y[j], z[j], j - ev_off[e], kl);
+    }
+}
+
+hipError_t launch_make_keys(const double* x, const double* y, const double* z,
+                            const int32_t* cstep, const uint32_t* ev_of, const uint32_t* ev_off,
+                            uint32_t n, KeyLayout kl, uint64_t* keys, hipStream_t s) {
+    make_keys<<<grid_for(n, 256, 8192), 256, 0, s>>>(x, y, z, cstep, ev_of, ev_off, n, kl, keys);
+    return hipGetLastError();
+}
+
+__global__ void count_active(const uint64_t* keys, const uint32_t* ev_off, uint32_t n_events,
+                             KeyLayout kl, int sources_all, uint32_t* ev_active,
+                             unsigned long long* pending) {
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n_events;
+         e += gridDim.x * blockDim.x) {
+        const uint32_t off = ev_off[e], ne = ev_off[e + 1] - off;
+        uint32_t lo = 0, hi = ne;  // first collected key of the segment in [lo, hi]
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (key_collected(keys[off + mid], kl))
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+        ev_active[e] = lo;
+        if (lo > 0) {
+            const unsigned long long src = sources_all ? ne : lo;
+            atomicAdd(&pending[0], (unsigned long long)lo);
+            atomicAdd(&pending[1], (unsigned long long)lo * src);
+        }
+    }
+}
+
+hipError_t launch_count(const uint64_t* keys, const uint32_t* ev_off, uint32_t n_events,
+                        KeyLayout kl, int sources_all, uint32_t* ev_active,
+                        unsigned long long* pending, hipStream_t s) {
+    count_active<<<grid_for(n_events, 256, 1024), 256, 0, s>>>(keys, ev_off, n_events, kl,
+                                                              sources_all, ev_active, pending);
+    return hipGetLastError();
+}
+
+// One workgroup per source tile g of event e = tile_event[g] (local tile
+// t = g - ev_tile[e]): positions of every slot of the tile, bounding box of
+// the slots that are sources.
+__global__ __launch_bounds__(kTile) void gather_tiles(
+    const uint64_t* keys, const uint32_t* ev_off, const uint32_t* ev_tile,
+    const uint32_t* tile_event, const uint32_t* ev_active, int sources_all, KeyLayout kl,
+    const double* x, const double* y, const double* z, double* px, double* py, double* pz,
+    double* box, uint32_t stride) {
     __shared__ double red[6][kTile / 64];
-    const uint32_t ns = count ? *count : count_c;
-    const uint32_t tile = blockIdx.x;
-    if (tile * kTile >= ns) return;  // uniform per workgroup
-    const uint32_t i = tile * kTile + threadIdx.x;
+    const uint32_t g = blockIdx.x;
+    const uint32_t e = tile_event[g];
+    const uint32_t t = g - ev_tile[e];
+    const uint32_t off = ev_off[e], ne = ev_off[e + 1] - off;
+    const uint32_t ns = sources_all ? ne : ev_active[e];
+    const uint32_t i = t * kTile + threadIdx.x;
     double lx = INFINITY, ly = INFINITY, lz = INFINITY;
     double hx = -INFINITY, hy = -INFINITY, hz = -INFINITY;
-    if (i < ns) {
-        // a list only holds real keys below its count; the clamp keeps every
-        // load inside the arrays regardless
-        const uint32_t c = min((uint32_t)(keys[i] & idx_mask), n_all - 1u);
-        lx = hx = px[i] = x[c];
-        ly = hy = py[i] = y[c];
-        lz = hz = pz[i] = z[c];
+    if (i < ne) {
+        // a slot of event e holds a key of event e; the clamp keeps every
+        // load inside the event regardless
+        const uint32_t c = off + min(key_local(keys[off + i], kl), ne - 1u);
+        const double vx = x[c], vy = y[c], vz = z[c];
+        px[off + i] = vx;
+        py[off + i] = vy;
+        pz[off + i] = vz;
+        if (i < ns) {
+            lx = hx = vx;
+            ly = hy = vy;
+            lz = hz = vz;
+        }
     }
-    if (!box) return;
     lx = wave_min(lx);
     ly = wave_min(ly);
     lz = wave_min(lz);
@@ -404,32 +515,18 @@ __global__ __launch_bounds__(kTile) void gather_tiles(const uint64_t* keys, cons
         const int k = threadIdx.x;
         double v = red[k][0];
         for (int w = 1; w < kTile / 64; ++w) v = (k < 3) ? fmin(v, red[k][w]) : fmax(v, red[k][w]);
-        box[(size_t)k * stride + tile] = v;
+        box[(size_t)k * stride + g] = v;
     }
 }
 
-hipError_t launch_gather(const uint64_t* keys, const uint32_t* count, uint32_t count_c,
-                         uint32_t bound, uint64_t idx_mask, uint32_t n_all, const double* x,
-                         const double* y, const double* z, double* px, double* py, double* pz,
-                         double* box, uint32_t stride, hipStream_t s) {
-    const uint32_t tiles = (bound + kTile - 1) / kTile;
-    if (tiles == 0) return hipSuccess;
-    gather_tiles<<<tiles, kTile, 0, s>>>(keys, count, count_c, idx_mask, n_all, x, y, z, px, py,
-                                         pz, box, stride);
-    return hipGetLastError();
-}
-
-hipError_t launch_field(const FieldArgs& a, int tpt, uint32_t nt_bound, hipStream_t s) {
-    const uint32_t per_block = (uint32_t)(kFieldThreads * tpt);
-    const uint64_t tblocks = ((uint64_t)nt_bound + per_block - 1) / per_block;
-    if (tblocks == 0) return hipSuccess;
-    const dim3 grid((uint32_t)(tblocks * (uint64_t)a.nchunk));
-    switch (tpt) {
-        case 1: field_tiles<1><<<grid, kFieldThreads, 0, s>>>(a); break;
-        case 2: field_tiles<2><<<grid, kFieldThreads, 0, s>>>(a); break;
-        case 4: field_tiles<4><<<grid, kFieldThreads, 0, s>>>(a); break;
-        default: return hipErrorInvalidValue;
-    }
+hipError_t launch_gather(const uint64_t* keys, const uint32_t* ev_off, const uint32_t* ev_tile,
+                         const uint32_t* tile_event, const uint32_t* ev_active, int sources_all,
+                         uint32_t n_tiles, KeyLayout kl, const double* x, const double* y,
+                         const double* z, double* px, double* py, double* pz, double* box,
+                         uint32_t stride, hipStream_t s) {
+    if (n_tiles == 0) return hipSuccess;
+    gather_tiles<<<n_tiles, kTile, 0, s>>>(keys, ev_off, ev_tile, tile_event, ev_active,
+                                           sources_all, kl, x, y, z, px, py, pz, box, stride);
     return hipGetLastError();
 }
 
@@ -437,7 +534,8 @@ hipError_t launch_field(const FieldArgs& a, int tpt, uint32_t nt_bound, hipStrea
 // Random diffusion vectors: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11),
 // ten rounds of two 32x32->64 multiplies whose high halves are XORed into the
 // other words together with the round key; the key advances by two Weyl
-// constants between rounds.  Counter = (carrier, step, event, 0).
+// constants between rounds.  Counter = (carrier within its event, step,
+// event, 0).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2,
                                               uint32_t& c3, uint32_t k0, uint32_t k1) {
@@ -467,130 +565,131 @@ __device__ __forceinline__ double unit_open(uint32_t w) {
 // (Eq. (1)) + Coulomb field (the chunk partials of field_tiles, summed in
 // FP64 in chunk order), |E|, mobility (Eq. (2)), drift mu E dt, diffusion
 // (Eqs. (3)-(4), Box-Muller on one Philox block), FP64 position update,
-// mirror at the back surface, collection at the well.  Holes that keep
-// travelling are appended to the next active list, one atomic per wave.
+// mirror at the back surface, collection at the well.
+//   list mode (Coulomb on): one thread per slot of the sorted list; every
+//     carrier keeps its slot in the next (unsorted) list with its new key,
+//     collected holes copying theirs through; the next sort restores order.
+//   carrier mode: one thread per carrier; travelling holes are counted, one
+//     atomic per wave.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kStepThreads) void step_update(StepArgs a) {
-    const uint32_t n_in = *a.cnt_in;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        *a.cnt_clear = 0u;  // counter of the step after next; nobody reads it now
-        if (n_in > 0) {
-            atomicAdd(&a.stats[0], (unsigned long long)n_in);
-            if (a.coulomb) {
-                unsigned long long nsrc = a.src_all ? a.n_all : n_in;
-                atomicAdd(&a.stats[1], (unsigned long long)n_in * nsrc);
-            }
+        unsigned long long holes, pairs = 0;
+        if (a.list_mode) {
+            holes = a.pending[0];
+            pairs = a.pending[1];
+        } else {
+            holes = *a.cnt_in;
+            *a.cnt_clear = 0u;  // counter of the step after next; nobody reads it now
+        }
+        if (holes > 0) {
+            atomicAdd(&a.stats[0], holes);
+            if (a.coulomb) atomicAdd(&a.stats[1], pairs);
             a.misc[1] = (int32_t)(a.step + 1u);
         }
     }
     const int lane = threadIdx.x & 63;
     const double two_pi = 6.283185307179586476925286766559;
-    const uint64_t idx_mask = (1ull << a.idx_bits) - 1ull;
-    // Full list: every carrier keeps its slot (collected ones copy their key
-    // through) and the next sort restores the order.  Otherwise: the
-    // travelling holes are appended, one atomic per wave.
-    const uint32_t limit = a.full_list ? a.n_all : n_in;
-    for (uint32_t base = blockIdx.x * kStepThreads; base < limit;
+    for (uint32_t base = blockIdx.x * kStepThreads; base < a.n_all;
          base += gridDim.x * kStepThreads) {
         const uint32_t slot = base + threadIdx.x;
         bool keep = false;
-        int32_t j = 0;
-        uint64_t key = kNoKey;
-        if (slot < n_in) {
-            j = (int32_t)min((uint32_t)(a.keys_in[slot] & idx_mask), a.n_all - 1u);
-            double ecx = 0.0, ecy = 0.0, ecz = 0.0;
-            if (a.coulomb) {
-                double sx = 0.0, sy = 0.0, sz = 0.0;
-                for (int c = 0; c < a.nchunk; ++c) {
-                    sx += (double)a.part[(size_t)(c * 3 + 0) * a.pstride + slot];
-                    sy += (double)a.part[(size_t)(c * 3 + 1) * a.pstride + slot];
-                    sz += (double)a.part[(size_t)(c * 3 + 2) * a.pstride + slot];
+        if (slot < a.n_all) {
+            uint32_t e, j, local;
+            bool active;
+            uint64_t key = 0;
+            if (a.list_mode) {
+                key = a.keys_in[slot];
+                e = key_event(key, a.kl);
+                const uint32_t off = a.ev_off[e], ne = a.ev_off[e + 1] - off;
+                local = min(key_local(key, a.kl), ne - 1u);
+                j = off + local;
+                active = slot - off < a.ev_active[e];
+            } else {
+                j = slot;
+                e = a.ev_of[j];
+                local = j - a.ev_off[e];
+                active = a.cstep[j] < 0;
+            }
+            if (active) {
+                double ecx = 0.0, ecy = 0.0, ecz = 0.0;
+                if (a.coulomb) {
+                    double sx = 0.0, sy = 0.0, sz = 0.0;
+                    const int nchunk = a.ev_chunks[e];
+                    for (int c = 0; c < nchunk; ++c) {
+                        sx += (double)a.part[(size_t)(c * 3 + 0) * a.pstride + slot];
+                        sy += (double)a.part[(size_t)(c * 3 + 1) * a.pstride + slot];
+                        sz += (double)a.part[(size_t)(c * 3 + 2) * a.pstride + slot];
+                    }
+                    ecx = a.K * sx;
+                    ecy = a.K * sy;
+                    ecz = a.K * sz;
                 }
-                ecx = a.K * sx;
-                ecy = a.K * sy;
-                ecz = a.K * sz;
+                const double x0 = a.x[j], y0 = a.y[j], z0 = a.z[j];
+                const double es = a.a1 * z0 - a.a2;
+                const double ex = ecx, ey = ecy, ez = ecz + es;
+                const double em = sqrt(ex * ex + ey * ey + ez * ez);
+                double mu = a.mu0;
+                if (a.mobility_model == 0)
+                    mu = a.mu0 / pow(1.0 + pow(em / a.ec, a.beta), a.inv_beta);
+                // v = mu E in cm/s; v dt in cm; 1 cm = 1e4 um
+                double dx = mu * ex * a.dt_s * 1e4;
+                double dy = mu * ey * a.dt_s * 1e4;
+                double dz = mu * ez * a.dt_s * 1e4;
+                if (a.diffusion) {
+                    uint32_t w0 = local, w1 = a.step, w2 = a.event0 + e, w3 = 0u;
+                    philox4x32_10(w0, w1, w2, w3, a.key0, a.key1);
+                    const double r01 = sqrt(-2.0 * log(unit_open(w0)));
+                    const double r23 = sqrt(-2.0 * log(unit_open(w2)));
+                    const double ang1 = two_pi * unit_open(w1);
+                    const double ang3 = two_pi * unit_open(w3);
+                    const double D = a.vt * mu;                        // Eq. (4), cm^2/s
+                    const double sigma = sqrt(2.0 * D * a.dt_s) * 1e4;  // Eq. (3), um
+                    dx += sigma * (r01 * cos(ang1));
+                    dy += sigma * (r01 * sin(ang1));
+                    dz += sigma * (r23 * cos(ang3));
+                }
+                const double xn = x0 + dx, yn = y0 + dy;
+                double zn = z0 + dz;
+                if (zn > a.thickness) zn = 2.0 * a.thickness - zn;
+                a.x[j] = xn;
+                a.y[j] = yn;
+                a.z[j] = zn;
+                if (!isfinite(xn) || !isfinite(yn) || !isfinite(zn)) atomicOr(&a.misc[0], 1);
+                const bool collected = zn <= a.z_well;
+                if (collected) a.cstep[j] = (int32_t)(a.step + 1u);
+                keep = !collected;
+                if (a.list_mode) key = make_key(e, collected, xn, yn, zn, local, a.kl);
             }
-            const double x0 = a.x[j], y0 = a.y[j], z0 = a.z[j];
-            const double es = a.a1 * z0 - a.a2;
-            const double ex = ecx, ey = ecy, ez = ecz + es;
-            const double em = sqrt(ex * ex + ey * ey + ez * ez);
-            double mu = a.mu0;
-            if (a.mobility_model == 0) mu = a.mu0 / pow(1.0 + pow(em / a.ec, a.beta), a.inv_beta);
-            // v = mu E in cm/s; v dt in cm; 1 cm = 1e4 um
-            double dx = mu * ex * a.dt_s * 1e4;
-            double dy = mu * ey * a.dt_s * 1e4;
-            double dz = mu * ez * a.dt_s * 1e4;
-            if (a.diffusion) {
-                uint32_t w0 = (uint32_t)j, w1 = a.step, w2 = a.event, w3 = 0u;
-                philox4x32_10(w0, w1, w2, w3, a.key0, a.key1);
-                const double r01 = sqrt(-2.0 * log(unit_open(w0)));
-                const double r23 = sqrt(-2.0 * log(unit_open(w2)));
-                const double ang1 = two_pi * unit_open(w1);
-                const double ang3 = two_pi * unit_open(w3);
-                const double D = a.vt * mu;                        // Eq. (4), cm^2/s
-                const double sigma = sqrt(2.0 * D * a.dt_s) * 1e4;  // Eq. (3), um
-                dx += sigma * (r01 * cos(ang1));
-                dy += sigma * (r01 * sin(ang1));
-                dz += sigma * (r23 * cos(ang3));
-            }
-            const double xn = x0 + dx, yn = y0 + dy;
-            double zn = z0 + dz;
-            if (zn > a.thickness) zn = 2.0 * a.thickness - zn;
-            a.x[j] = xn;
-            a.y[j] = yn;
-            a.z[j] = zn;
-            if (!isfinite(xn) || !isfinite(yn) || !isfinite(zn)) atomicOr(&a.misc[0], 1);
-            const bool collected = zn <= a.z_well;
-            if (collected) a.cstep[j] = (int32_t)(a.step + 1u);
-            keep = !collected;
-            key = spatial_key(xn, yn, zn, (uint32_t)j, a.idx_bits, collected);
-        } else if (slot < limit) {
-            key = a.keys_in[slot];  // collected: frozen, key unchanged
+            if (a.list_mode) a.keys_out[slot] = key;
         }
-        const unsigned long long m = __ballot(keep);
-        uint32_t wbase = 0;
-        if (m) {
-            const int leader = __ffsll((long long)m) - 1;
-            if (lane == leader) wbase = atomicAdd(a.cnt_out, (uint32_t)__popcll(m));
-            wbase = __shfl(wbase, leader);
-        }
-        if (a.full_list) {
-            if (slot < limit) a.keys_out[slot] = key;
-        } else if (keep) {
-            const unsigned long long below = (lane == 0) ? 0ull : (m << (64 - lane));
-            a.keys_out[wbase + (uint32_t)__popcll(below)] = key;
+        if (!a.list_mode) {
+            const unsigned long long m = __ballot(keep);
+            if (m && lane == __ffsll((long long)m) - 1)
+                atomicAdd(a.cnt_out, (uint32_t)__popcll(m));
         }
     }
 }
 
-static uint32_t grid_for(uint64_t n, int threads, uint32_t cap) {
-    uint64_t g = (n + (uint64_t)threads - 1) / (uint64_t)threads;
-    if (g < 1) g = 1;
-    if (g > cap) g = cap;
-    return (uint32_t)g;
-}
-
-hipError_t launch_step(const StepArgs& a, uint32_t n_bound, hipStream_t s) {
-    const uint32_t slots = a.full_list ? a.n_all : n_bound;
-    step_update<<<grid_for(slots, kStepThreads, 8192), kStepThreads, 0, s>>>(a);
+hipError_t launch_step(const StepArgs& a, uint32_t n_slots, hipStream_t s) {
+    step_update<<<grid_for(n_slots, kStepThreads, 16384), kStepThreads, 0, s>>>(a);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // Load-time boundary handling: mirror z beyond the back surface, collect
-// holes at or below the well (collection step 0), list the others.
+// holes at or below the well (collection step 0), record each carrier's
+// event, count the travelling ones.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kStepThreads) void load_prepare(double* z, int32_t* cstep,
-                                                             uint64_t* keys, uint32_t* cnt,
-                                                             const double* x, const double* y,
-                                                             uint32_t n, uint32_t idx_bits,
-                                                             int full_list, double thickness,
-                                                             double z_well) {
+                                                             const uint32_t* ev_off,
+                                                             uint32_t* ev_of, uint32_t n_events,
+                                                             uint32_t n, double thickness,
+                                                             double z_well, uint32_t* cnt) {
     const int lane = threadIdx.x & 63;
     for (uint32_t base = blockIdx.x * kStepThreads; base < n; base += gridDim.x * kStepThreads) {
         const uint32_t j = base + threadIdx.x;
         bool keep = false;
-        uint64_t key = kNoKey;
         if (j < n) {
             double zz = z[j];
             if (zz > thickness) zz = 2.0 * thickness - zz;
@@ -598,42 +697,18 @@ __global__ __launch_bounds__(kStepThreads) void load_prepare(double* z, int32_t*
             const bool collected = zz <= z_well;
             cstep[j] = collected ? 0 : -1;
             keep = !collected;
-            key = spatial_key(x[j], y[j], zz, j, idx_bits, collected);
+            ev_of[j] = event_of(ev_off, n_events, j);
         }
         const unsigned long long m = __ballot(keep);
-        uint32_t wbase = 0;
-        if (m) {
-            const int leader = __ffsll((long long)m) - 1;
-            if (lane == leader) wbase = atomicAdd(cnt, (uint32_t)__popcll(m));
-            wbase = __shfl(wbase, leader);
-        }
-        if (full_list) {
-            if (j < n) keys[j] = key;
-        } else if (keep) {
-            const unsigned long long below = (lane == 0) ? 0ull : (m << (64 - lane));
-            keys[wbase + (uint32_t)__popcll(below)] = key;
-        }
+        if (m && lane == __ffsll((long long)m) - 1) atomicAdd(cnt, (uint32_t)__popcll(m));
     }
 }
 
-hipError_t launch_load(double* z, int32_t* cstep, uint64_t* keys, uint32_t* cnt, const double* x,
-                       const double* y, uint32_t n, uint32_t idx_bits, int full_list,
-                       double thickness, double z_well, hipStream_t s) {
+hipError_t launch_load(double* z, int32_t* cstep, const uint32_t* ev_off, uint32_t* ev_of,
+                       uint32_t n_events, uint32_t n, double thickness, double z_well,
+                       uint32_t* cnt, hipStream_t s) {
     load_prepare<<<grid_for(n, kStepThreads, 8192), kStepThreads, 0, s>>>(
-        z, cstep, keys, cnt, x, y, n, idx_bits, full_list, thickness, z_well);
-    return hipGetLastError();
-}
-
-// Keys of every carrier, in carrier order (targets of gccd_field).
-__global__ void keys_all(const double* x, const double* y, const double* z, uint32_t n,
-                         uint32_t idx_bits, uint64_t* keys) {
-    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x)
-        keys[j] = spatial_key(x[j], y[j], z[j], j, idx_bits, false);
-}
-
-hipError_t launch_keys_all(const double* x, const double* y, const double* z, uint32_t n,
-                           uint32_t idx_bits, uint64_t* keys, hipStream_t s) {
-    keys_all<<<grid_for(n, 256, 8192), 256, 0, s>>>(x, y, z, n, idx_bits, keys);
+        z, cstep, ev_off, ev_of, n_events, n, thickness, z_well, cnt);
     return hipGetLastError();
 }
 
@@ -649,71 +724,69 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
     return hipGetLastError();
 }
 
-__global__ void fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * blockDim.x)
-        p[i] = v;
-}
-
-hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    fill_u64<<<grid_for(n, 256, 4096), 256, 0, s>>>(p, n, v);
-    return hipGetLastError();
-}
-
 // Coulomb field of every carrier for gccd_field: chunk partials summed in
 // FP64 in chunk order, times K (same reduction as step_update), written back
 // to the carrier each slot holds.
-__global__ void field_finish(const float* part, uint32_t pstride, int nchunk,
-                             const uint64_t* tkeys, uint64_t idx_mask, uint32_t n, double K,
-                             double* ex, double* ey, double* ez) {
+__global__ void field_finish(const float* part, uint32_t pstride, const int32_t* ev_chunks,
+                             const uint64_t* keys, const uint32_t* ev_off, KeyLayout kl,
+                             uint32_t n, double K, double* ex, double* ey, double* ez) {
     for (uint32_t slot = blockIdx.x * blockDim.x + threadIdx.x; slot < n;
          slot += gridDim.x * blockDim.x) {
+        const uint64_t key = keys[slot];
+        const uint32_t e = key_event(key, kl);
+        const uint32_t off = ev_off[e], ne = ev_off[e + 1] - off;
+        const uint32_t j = off + min(key_local(key, kl), ne - 1u);
         double sx = 0.0, sy = 0.0, sz = 0.0;
+        const int nchunk = ev_chunks[e];
         for (int c = 0; c < nchunk; ++c) {
             sx += (double)part[(size_t)(c * 3 + 0) * pstride + slot];
             sy += (double)part[(size_t)(c * 3 + 1) * pstride + slot];
             sz += (double)part[(size_t)(c * 3 + 2) * pstride + slot];
         }
-        const uint32_t j = min((uint32_t)(tkeys[slot] & idx_mask), n - 1u);
         ex[j] = K * sx;
         ey[j] = K * sy;
         ez[j] = K * sz;
     }
 }
 
-hipError_t launch_field_finish(const float* part, uint32_t pstride, int nchunk,
-                               const uint64_t* tkeys, uint64_t idx_mask, uint32_t n, double K,
-                               double* ex, double* ey, double* ez, hipStream_t s) {
-    field_finish<<<grid_for(n, 256, 8192), 256, 0, s>>>(part, pstride, nchunk, tkeys, idx_mask, n,
-                                                         K, ex, ey, ez);
+hipError_t launch_field_finish(const float* part, uint32_t pstride, const int32_t* ev_chunks,
+                               const uint64_t* keys, const uint32_t* ev_off, KeyLayout kl,
+                               uint32_t n, double K, double* ex, double* ey, double* ez,
+                               hipStream_t s) {
+    field_finish<<<grid_for(n, 256, 8192), 256, 0, s>>>(part, pstride, ev_chunks, keys, ev_off,
+                                                         kl, n, K, ex, ey, ez);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // Sec. V.A image: half-open pixels, index floor((x - x0) / pitch) in IEEE
-// FP64 (correctly rounded division), integer atomics into the caller's grid.
+// FP64 (correctly rounded division), integer atomics into the caller's grid:
+// one grid for all events, or one per event (per_event).
 // ---------------------------------------------------------------------------
-__global__ void image_bin(const double* x, const double* y, const int32_t* cstep, uint32_t n,
-                          double x0, double y0, double pitch, int32_t nx, int32_t ny,
-                          uint32_t* counts, unsigned long long* n_out) {
+__global__ void image_bin(const double* x, const double* y, const int32_t* cstep,
+                          const uint32_t* ev_of, uint32_t n, int per_event, double x0, double y0,
+                          double pitch, int32_t nx, int32_t ny, uint32_t* counts,
+                          unsigned long long* n_out) {
     for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
         if (cstep[j] < 0) continue;
+        const uint64_t e = per_event ? (uint64_t)ev_of[j] : 0ull;
         const double fx = floor((x[j] - x0) / pitch);
         const double fy = floor((y[j] - y0) / pitch);
         if (fx >= 0.0 && fx < (double)nx && fy >= 0.0 && fy < (double)ny) {
-            atomicAdd(&counts[(int64_t)fy * nx + (int64_t)fx], 1u);
+            atomicAdd(&counts[e * (uint64_t)nx * (uint64_t)ny + (uint64_t)fy * nx + (uint64_t)fx],
+                      1u);
         } else {
-            atomicAdd(n_out, 1ull);
+            atomicAdd(&n_out[e], 1ull);
         }
     }
 }
 
-hipError_t launch_image(const double* x, const double* y, const int32_t* cstep, uint32_t n,
-                        double x0, double y0, double pitch, int32_t nx, int32_t ny,
-                        uint32_t* counts, unsigned long long* n_out, hipStream_t s) {
-    image_bin<<<grid_for(n, 256, 8192), 256, 0, s>>>(x, y, cstep, n, x0, y0, pitch, nx, ny,
-                                                      counts, n_out);
+hipError_t launch_image(const double* x, const double* y, const int32_t* cstep,
+                        const uint32_t* ev_of, uint32_t n, int per_event, double x0, double y0,
+                        double pitch, int32_t nx, int32_t ny, uint32_t* counts,
+                        unsigned long long* n_out, hipStream_t s) {
+    image_bin<<<grid_for(n, 256, 8192), 256, 0, s>>>(x, y, cstep, ev_of, n, per_event, x0, y0,
+                                                      pitch, nx, ny, counts, n_out);
     return hipGetLastError();
 }
 

@@ -24,9 +24,10 @@ GCCD_E_NOMEM = -4
 GCCD_E_NONFINITE = -5
 
 # every symbol the header declares
-EXPORTS = ("gccd_init", "gccd_load", "gccd_run", "gccd_image", "gccd_field",
-           "gccd_positions", "gccd_stats", "gccd_set_launch", "gccd_set_timing",
-           "gccd_strerror", "gccd_last_error", "gccd_destroy")
+EXPORTS = ("gccd_init", "gccd_load", "gccd_load_events", "gccd_run", "gccd_image",
+           "gccd_image_events", "gccd_field", "gccd_positions", "gccd_stats",
+           "gccd_set_launch", "gccd_set_timing", "gccd_strerror", "gccd_last_error",
+           "gccd_destroy")
 
 
 class CParams(ctypes.Structure):
@@ -61,6 +62,8 @@ class CStats(ctypes.Structure):
         ("field_launches", ctypes.c_int64),
         ("targets_per_thread", ctypes.c_int32),
         ("source_chunks", ctypes.c_int32),
+        ("n_events", ctypes.c_int64),
+        ("max_source_chunks", ctypes.c_int64),
     ]
 
 
@@ -72,6 +75,8 @@ def _load():
     P, i32, i64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     L.gccd_init.argtypes = [ctypes.POINTER(CParams), P, ctypes.POINTER(P)]
     L.gccd_load.argtypes = [P, i64, P, P, P]
+    L.gccd_load_events.argtypes = [P, i32, P, P, P, P]
+    L.gccd_image_events.argtypes = [P, d, d, d, i32, i32, P, P]
     L.gccd_run.argtypes = [P, d, i64, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.gccd_image.argtypes = [P, d, d, d, i32, i32, P, P]
     L.gccd_field.argtypes = [P, P, P, P]
@@ -166,6 +171,16 @@ def gccd_load(ctx: int, x: torch.Tensor, y: torch.Tensor, z: torch.Tensor) -> No
     _check(ctx, lib.gccd_load(ctx, n, _f64_dev(x, n), _f64_dev(y, n), _f64_dev(z, n)))
 
 
+def gccd_load_events(ctx: int, offsets, x: torch.Tensor, y: torch.Tensor,
+                     z: torch.Tensor) -> None:
+    """offsets: n_events + 1 carrier offsets (host sequence); event e holds
+    carriers [offsets[e], offsets[e+1]) of the device arrays x, y, z."""
+    off = (ctypes.c_int64 * len(offsets))(*[int(v) for v in offsets])
+    n = int(offsets[-1])
+    _check(ctx, lib.gccd_load_events(ctx, len(offsets) - 1, off, _f64_dev(x, n),
+                                     _f64_dev(y, n), _f64_dev(z, n)))
+
+
 def gccd_run(ctx: int, dt_ps: float, max_steps: int):
     """Returns (steps_done, n_active)."""
     done, na = ctypes.c_int64(0), ctypes.c_int64(0)
@@ -186,6 +201,17 @@ def gccd_image(ctx: int, x0_um: float, y0_um: float, pitch_um: float, nx: int, n
         raise ValueError("counts must be a contiguous uint32 tensor of ny*nx elements")
     _check(ctx, lib.gccd_image(ctx, float(x0_um), float(y0_um), float(pitch_um), int(nx),
                                int(ny), counts.data_ptr(), n_outside.data_ptr()))
+    return counts, n_outside
+
+
+def gccd_image_events(ctx: int, n_events: int, x0_um: float, y0_um: float, pitch_um: float,
+                      nx: int, ny: int):
+    """Returns (counts[n_events, ny, nx] uint32, n_outside[n_events] uint64) device tensors."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    counts = torch.empty((n_events, ny, nx), dtype=torch.uint32, device=dev)
+    n_outside = torch.empty(n_events, dtype=torch.uint64, device=dev)
+    _check(ctx, lib.gccd_image_events(ctx, float(x0_um), float(y0_um), float(pitch_um), int(nx),
+                                      int(ny), counts.data_ptr(), n_outside.data_ptr()))
     return counts, n_outside
 
 

@@ -29,7 +29,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported(g):
     names = declared_functions()
-    assert len(names) == 12
+    assert len(names) == 14
     for name in names:
         assert hasattr(g.lib, name), name
     assert sorted(g.EXPORTS) == names
@@ -44,15 +44,17 @@ def test_struct_layout_matches_header(g, tmp_path):
         'printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(gccd_params),'
         " offsetof(gccd_params, thickness_um), offsetof(gccd_params, coulomb),"
         " offsetof(gccd_params, seed), offsetof(gccd_params, event), sizeof(gccd_stats_t));\n"
-        'printf("%zu %zu\\n", offsetof(gccd_stats_t, field_ms),'
-        " offsetof(gccd_stats_t, source_chunks));\nreturn 0;}\n")
+        'printf("%zu %zu %zu\\n", offsetof(gccd_stats_t, field_ms),'
+        " offsetof(gccd_stats_t, source_chunks), offsetof(gccd_stats_t, max_source_chunks));"
+        "\nreturn 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o",
                     str(exe)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
     P, S = g.CParams, g.CStats
     want = [ctypes.sizeof(P), P.thickness_um.offset, P.coulomb.offset, P.seed.offset,
-            P.event.offset, ctypes.sizeof(S), S.field_ms.offset, S.source_chunks.offset]
+            P.event.offset, ctypes.sizeof(S), S.field_ms.offset, S.source_chunks.offset,
+            S.max_source_chunks.offset]
     assert list(map(int, out)) == want
 
 
@@ -93,6 +95,8 @@ def test_null_arguments(g):
     out = ctypes.c_void_p()
     assert L.gccd_init(None, None, ctypes.byref(out)) == g.GCCD_E_INVALID
     assert L.gccd_load(None, 10, None, None, None) == g.GCCD_E_INVALID
+    assert L.gccd_load_events(None, 1, None, None, None, None) == g.GCCD_E_INVALID
+    assert L.gccd_image_events(None, 0.0, 0.0, 15.0, 4, 4, None, None) == g.GCCD_E_INVALID
     assert L.gccd_run(None, 10.0, 1, None, None) == g.GCCD_E_INVALID
     assert L.gccd_image(None, 0.0, 0.0, 15.0, 4, 4, None, None) == g.GCCD_E_INVALID
     assert L.gccd_field(None, None, None, None) == g.GCCD_E_INVALID
