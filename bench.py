@@ -40,10 +40,34 @@ def measured_traffic(n: int, tpt: int, chunks: int):
             sha = hashlib.sha256(f.read()).hexdigest()
     except (OSError, KeyError, ValueError):
         return None
-    if (sha != rec.get("kernel_source_sha256") or n != 100000
+    if (sha != rec.get("kernel_source_sha256") or n != rec.get("n_holes", 100000)
             or tpt != rec.get("targets_per_thread") or chunks != rec.get("source_chunks")):
         return None
     return rec["hbm_bytes_per_launch"]
+
+
+def cpu_baseline_batch(events, dev_dict, dt_ps, n_sample: int = 32, seed: int = 5) -> dict:
+    """The oracle on a bounded sample of the batch: one time step of each of
+    n_sample events drawn at random (each event alone, as the physics has it)."""
+    import numpy as np
+    import oracle
+    rng = np.random.default_rng(seed)
+    pick = rng.choice(len(events), size=min(n_sample, len(events)), replace=False)
+    pairs = 0
+    t0 = time.perf_counter()
+    for e in pick:
+        x, y, z = events[e]
+        dev = oracle.Device(**dict(dev_dict))
+        dev.event = int(dev_dict["event"]) + int(e)
+        st = oracle.State(dev, x, y, z)
+        na = st.n_active
+        st.run(dt_ps, 1)
+        pairs += na * len(x)
+    dt = time.perf_counter() - t0
+    return {"value": pairs / dt, "unit": "pair-interactions/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"one time step of {len(pick)} randomly drawn events of the batch, FP64, "
+                      f"{dt:.1f} s wall"}
 
 
 def cpu_baseline(w, max_seconds: float = 12.0) -> dict:
@@ -74,7 +98,11 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", choices=("cloud", "batch"), default="cloud",
+                    help="cloud: one 1e5-hole cloud (default); batch: 4096 clouds of "
+                         "200-20000 holes in one launch")
     ap.add_argument("--n", type=int, default=100000)
+    ap.add_argument("--events", type=int, default=4096)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--tpt", type=int, default=0, help="targets per thread (0 = auto)")
     ap.add_argument("--chunks", type=int, default=0, help="source chunks (0 = auto)")
@@ -92,7 +120,15 @@ def main() -> int:
     from paper_2203_11043_amd import gccd, workloads
 
     torch.cuda.set_device(0)
-    w = workloads.single_cloud(args.n, seed=args.seed)
+    import numpy as np
+    if args.workload == "batch":
+        events = workloads.batch_of_clouds(args.events, seed=args.seed)
+        sizes = [len(e[0]) for e in events]
+        offsets = np.concatenate([[0], np.cumsum(sizes)]).tolist()
+        w = workloads.Workload(f"batch_{args.events}", *(np.concatenate([e[k] for e in events])
+                                                        for k in range(3)))
+    else:
+        w = workloads.single_cloud(args.n, seed=args.seed)
     if args.copy_calibration_mib:
         a = torch.empty(args.copy_calibration_mib * (1 << 20) // 4, dtype=torch.float32,
                         device="cuda").fill_(1.0)
@@ -105,13 +141,20 @@ def main() -> int:
     ctx = gccd.gccd_init(params)
     gccd.gccd_set_launch(ctx, args.tpt, args.chunks)
     xs = [torch.as_tensor(v).cuda() for v in (w.x, w.y, w.z)]
-    gccd.gccd_load(ctx, *xs)
-    counts = torch.empty((w.ny, w.nx), dtype=torch.uint32, device="cuda")
-    nout = torch.empty(1, dtype=torch.uint64, device="cuda")
+    if args.workload == "batch":
+        gccd.gccd_load_events(ctx, offsets, *xs)
 
-    def step():
-        gccd.gccd_run(ctx, w.dt_ps, 1)
-        gccd.gccd_image(ctx, 0.0, 0.0, w.pitch_um, w.nx, w.ny, counts, nout)
+        def step():
+            gccd.gccd_run(ctx, w.dt_ps, 1)
+            gccd.gccd_image_events(ctx, args.events, 0.0, 0.0, w.pitch_um, w.nx, w.ny)
+    else:
+        gccd.gccd_load(ctx, *xs)
+        counts = torch.empty((w.ny, w.nx), dtype=torch.uint32, device="cuda")
+        nout = torch.empty(1, dtype=torch.uint64, device="cuda")
+
+        def step():
+            gccd.gccd_run(ctx, w.dt_ps, 1)
+            gccd.gccd_image(ctx, 0.0, 0.0, w.pitch_um, w.nx, w.ny, counts, nout)
 
     for _ in range(args.warmup):
         step()
@@ -149,15 +192,22 @@ def main() -> int:
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"single Gaussian hole cloud, exact all-pairs path: n={w.n}, "
-                        f"sigma={workloads.cloud_sigma(w.n):.3f} um, depth {w.z.mean():.1f} um; "
-                        "675 um CCD at 140 K, dt 10 ps, 64x64 image of 15 um pixels",
+            "workload": (f"single Gaussian hole cloud, exact all-pairs path: n={w.n}, "
+                         f"sigma={workloads.cloud_sigma(w.n):.3f} um, depth {w.z.mean():.1f} um; "
+                         "675 um CCD at 140 K, dt 10 ps, 64x64 image of 15 um pixels")
+            if args.workload == "cloud" else
+            (f"{args.events} independent Gaussian clouds in one launch, exact all-pairs path: "
+             f"holes log-uniform in [200, 20000] (total {w.n}), sigma 0.5 um x (n/1000)^(1/3), "
+             "depth uniform over 675 um; 140 K, dt 10 ps, one 64x64 image of 15 um pixels per "
+             "event"),
             "n_holes": w.n,
+            "n_events": s1["n_events"],
             "time_steps_per_step": 1,
             "positions": "f64",
             "pair_arithmetic": "f32 (double-single coordinate differences)",
             "targets_per_thread": s1["targets_per_thread"],
             "source_chunks": s1["source_chunks"],
+            "max_source_chunks": s1["max_source_chunks"],
         },
         "carrier_steps_per_s": csteps / elapsed,
         "pct_fp32_peak": 100.0 * FLOP_PER_PAIR * pair_rate / (PEAK_FP32_TFLOPS * 1e12),
@@ -176,7 +226,8 @@ def main() -> int:
         },
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w)
+        out["cpu_baseline"] = (cpu_baseline(w) if args.workload == "cloud" else
+                               cpu_baseline_batch(events, w.device, w.dt_ps))
     print(json.dumps(out), flush=True)
     return 0
 
