@@ -23,7 +23,8 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_build", "liboracle.so")
+# ORACLE_LIB lets the mutation test point the pins at a deliberately broken build
+LIB_PATH = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "_build", "liboracle.so")
 SOURCES = [os.path.join(_HERE, "gccd_oracle.c")]
 
 

@@ -407,3 +407,19 @@ def test_image_bins_by_hand(orc):
     assert out == 3     # x = 60, x < 0, NaN; the active carrier is not binned
     c2, o2 = orc.image([100.0, 101.0], [100.0, 100.0], [0, 0], 95.0, 90.0, 5.0, 3, 3)
     assert c2[2, 1] == 2 and o2 == 0
+
+
+def test_back_surface_mirror_folds_the_gaussian(orc):
+    """Diffusion only, starting on the back surface: mirroring at the surface
+    folds the free Gaussian, so the depth below it is half-normal with mean
+    sigma sqrt(2/pi) and variance sigma^2 (1 - 2/pi); sigma^2 is measured on
+    the unmirrored x axis of the same run."""
+    d = dev(orc, coulomb=0, a1=0.0, a2=0.0, seed=17)
+    n, t = 40000, d.thickness_um
+    st = orc.State(d, np.zeros(n), np.zeros(n), np.full(n, t))
+    st.run(10.0, 100)
+    assert st.n_active == n and np.all(st.z <= t)
+    s2 = 0.5 * (st.x.var() + st.y.var())
+    depth = t - st.z
+    assert abs(depth.mean() / math.sqrt(2.0 * s2 / math.pi) - 1.0) < 0.02
+    assert abs(depth.var() / (s2 * (1.0 - 2.0 / math.pi)) - 1.0) < 0.04
