@@ -176,6 +176,39 @@ int gccd_stats(gccd_ctx* c, gccd_stats_t* out);
  * stream.  GCCD_E_INVALID outside those ranges. */
 int gccd_set_launch(gccd_ctx* c, int32_t targets_per_thread, int32_t source_chunks);
 
+/* Arithmetic of the Eq. (6) pair sum.  The paper keeps positions as single
+ * precision floats and gives no error analysis; these modes measure what
+ * each design choice costs and buys.  Every FP32 mode forms pair
+ * differences, r^2, r^-3 (hardware reciprocal square root, cubed) and the
+ * per-tile sums in FP32; they differ in the origin the coordinates are
+ * rounded relative to and in how the difference of a pair is formed.
+ *   DEFAULT   origin at the centre of each workgroup's targets; pairs closer
+ *             than a quarter of the targets' half-diagonal recomputed from
+ *             the residuals of the coordinates (the fast, bounded mode)
+ *   BLOCK     the same origins, no close-pair recomputation
+ *   EVENT     one origin per event (the centre of its sources' bounding
+ *             box), no recomputation
+ *   ABSOLUTE  no origin: FP32 absolute coordinates, as the paper stores them
+ *   COMPENSATED  workgroup origins; every pair's difference formed from the
+ *             coordinates and their residuals (double-single differences)
+ *   FP64      every pair in FP64 (difference, r^2, r^-3 = 1/(q sqrt q)) and
+ *             FP64 sums; reference quality, several times slower */
+enum {
+    GCCD_PRECISION_DEFAULT = 0,
+    GCCD_PRECISION_BLOCK = 1,
+    GCCD_PRECISION_EVENT = 2,
+    GCCD_PRECISION_ABSOLUTE = 3,
+    GCCD_PRECISION_COMPENSATED = 4,
+    GCCD_PRECISION_FP64 = 5
+};
+
+/* Selects the arithmetic of the Eq. (6) kernel (GCCD_PRECISION_*) for gccd_run
+ * and gccd_field.  The FP64 mode keeps each chunk's sum as two FP32 partial
+ * groups and so splits a target's sum into at most 32 source chunks (a
+ * larger gccd_set_launch value is clamped).  Applies to the current load and
+ * later ones; synchronises the stream.  GCCD_E_INVALID for an unknown mode. */
+int gccd_set_precision(gccd_ctx* c, int32_t mode);
+
 /* on = 1 times every Eq. (6) launch with HIP events on the context's stream
  * (reported by gccd_stats); on = 0 stops timing. */
 int gccd_set_timing(gccd_ctx* c, int32_t on);

@@ -60,9 +60,11 @@ struct gccd_ctx {
     std::vector<uint32_t> off_h;   // [E+1] first carrier of each event
     std::vector<uint32_t> tile_h;  // [E+1] first source tile of each event
     std::vector<int32_t> chunks_h; // [E] chunks of each event's field sum
+    std::vector<int32_t> groups_h; // [E] partial-sum groups (2x chunks in the FP64 mode)
     std::vector<uint32_t> order_h; // events by decreasing size (work-item order)
     uint32_t n_tiles = 0;
     int max_chunks = 1;
+    int max_groups = 1;
 
     double* x = nullptr;
     double* y = nullptr;
@@ -94,6 +96,7 @@ struct gccd_ctx {
 
     int tpt_fixed = 0, chunks_fixed = 0;
     int tpt = 1;
+    int precision = GCCD_PRECISION_DEFAULT;
 
     bool timing = false;
     std::vector<hipEvent_t> ev;
@@ -190,7 +193,8 @@ uint32_t bits_for(uint64_t count) {  // smallest b with 2^b >= count (0 for coun
 // still travel: every step of a load, and gccd_field, sum in the same order.
 // Enough workgroups to fill the chip (about 48 waves per SIMD in total,
 // which also evens out workgroups that meet more close pairs), at most 3072
-// sources per chunk, and at least 4 tiles per chunk.
+// sources per chunk, and at least 4 tiles per chunk.  The FP64 mode stores
+// each chunk's sum in two groups and so takes at most kMaxChunks / 2 chunks.
 void choose_chunks(gccd_ctx* c) {
     uint64_t tblocks = 0;
     for (uint32_t e = 0; e < c->n_events; ++e)
@@ -198,7 +202,11 @@ void choose_chunks(gccd_ctx* c) {
                    (kFieldThreads * c->tpt);
     const uint64_t want = (uint64_t)c->n_cu * 48;
     c->chunks_h.assign(c->n_events, 1);
+    c->groups_h.assign(c->n_events, 1);
     c->max_chunks = 1;
+    c->max_groups = 1;
+    const bool split = c->precision == GCCD_PRECISION_FP64;
+    const uint64_t cap = split ? kMaxChunks / 2 : kMaxChunks;
     for (uint32_t e = 0; e < c->n_events; ++e) {
         const uint64_t ne = c->off_h[e + 1] - c->off_h[e];
         const uint64_t tiles = (ne + kTile - 1) / kTile;
@@ -208,11 +216,13 @@ void choose_chunks(gccd_ctx* c) {
         } else {
             s = std::max<uint64_t>((ne + 3071) / 3072, (want + tblocks - 1) / tblocks);
             s = std::min<uint64_t>(s, std::max<uint64_t>(1, tiles / 4));
-            s = std::min<uint64_t>(s, kMaxChunks);
             s = std::max<uint64_t>(s, 1);
         }
+        s = std::min<uint64_t>(s, cap);
         c->chunks_h[e] = (int32_t)s;
+        c->groups_h[e] = (int32_t)(split ? 2 * s : s);
         c->max_chunks = std::max(c->max_chunks, (int)s);
+        c->max_groups = std::max(c->max_groups, c->groups_h[e]);
     }
 }
 
@@ -249,12 +259,12 @@ int size_chunk_buffers(gccd_ctx* c) {
         items += (size_t)((ne + kFieldThreads - 1) / kFieldThreads) * (size_t)c->chunks_h[e];
     }
     c->items_cap = std::max<size_t>(items, 1);
-    if (hipMalloc(&c->part, (size_t)c->max_chunks * 3 * (size_t)c->n * sizeof(float)) !=
+    if (hipMalloc(&c->part, (size_t)c->max_groups * 3 * (size_t)c->n * sizeof(float)) !=
             hipSuccess ||
         hipMalloc(&c->items_d, c->items_cap * sizeof(FieldItem)) != hipSuccess ||
         hipHostMalloc((void**)&c->host_items, c->items_cap * sizeof(FieldItem)) != hipSuccess)
         return fail(c, GCCD_E_NOMEM, "device allocation of the field buffers failed");
-    GCCD_HIP(c, hipMemcpyAsync(c->ev_chunks_d, c->chunks_h.data(), c->n_events * sizeof(int32_t),
+    GCCD_HIP(c, hipMemcpyAsync(c->ev_chunks_d, c->groups_h.data(), c->n_events * sizeof(int32_t),
                                hipMemcpyHostToDevice, c->stream));
     GCCD_HIP(c, hipStreamSynchronize(c->stream));
     return GCCD_OK;
@@ -308,6 +318,7 @@ FieldArgs field_args(const gccd_ctx* c, bool targets_all) {
     fa.tile_box = c->tile_box;
     fa.tile_stride = std::max<uint32_t>(c->n_tiles, 1);
     fa.eps2 = (float)(c->p.softening_um * c->p.softening_um);
+    fa.eps2d = c->p.softening_um * c->p.softening_um;
     fa.part = c->part;
     fa.pstride = (uint32_t)c->n;
     return fa;
@@ -554,6 +565,23 @@ int gccd_set_launch(gccd_ctx* c, int32_t tpt, int32_t chunks) {
     return GCCD_OK;
 }
 
+int gccd_set_precision(gccd_ctx* c, int32_t mode) {
+    if (!c) return GCCD_E_INVALID;
+    if (mode < GCCD_PRECISION_DEFAULT || mode > GCCD_PRECISION_FP64)
+        return fail(c, GCCD_E_INVALID, "gccd_set_precision: unknown mode");
+    c->precision = mode;
+    if (c->loaded) {
+        GCCD_HIP(c, hipStreamSynchronize(c->stream));
+        choose_chunks(c);
+        int r = size_chunk_buffers(c);
+        if (r != GCCD_OK) {
+            free_buffers(c);
+            return r;
+        }
+    }
+    return GCCD_OK;
+}
+
 int gccd_set_timing(gccd_ctx* c, int32_t on) {
     if (!c || (on | 1) != 1) return GCCD_E_INVALID;
     c->timing = on != 0;
@@ -624,7 +652,7 @@ int gccd_run(gccd_ctx* c, double dt_ps, int64_t max_steps, int64_t* steps_done,
                 hipEvent_t* evp = nullptr;
                 int r = record_field_start(c, &evp);
                 if (r != GCCD_OK) return r;
-                GCCD_HIP(c, launch_field(fa, c->tpt, c->n_items, c->stream));
+                GCCD_HIP(c, launch_field(fa, c->tpt, c->precision, c->n_items, c->stream));
                 if (evp) GCCD_HIP(c, hipEventRecord(evp[1], c->stream));
                 sa.keys_in = c->keys[c->cur];
                 sa.keys_out = c->keys[c->cur ^ 1];
@@ -689,7 +717,7 @@ int gccd_field(gccd_ctx* c, double* ex, double* ey, double* ez) {
     int r = build_items(c, all.data());
     if (r != GCCD_OK) return r;
     FieldArgs fa = field_args(c, true);
-    GCCD_HIP(c, launch_field(fa, c->tpt, c->n_items, c->stream));
+    GCCD_HIP(c, launch_field(fa, c->tpt, c->precision, c->n_items, c->stream));
     GCCD_HIP(c, launch_field_finish(c->part, n, c->ev_chunks_d, c->keys[c->cur], c->ev_off_d,
                                     c->kl, n, c->K, ex, ey, ez, c->stream));
     GCCD_HIP(c, hipStreamSynchronize(c->stream));  // host_items may be rebuilt next

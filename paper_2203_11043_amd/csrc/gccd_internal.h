@@ -49,7 +49,9 @@ struct FieldArgs {
     const double* tile_box;     // [6][tile_stride] boxes of the source tiles
     uint32_t tile_stride;
     float eps2;                 // softening length squared, um^2
-    float* part;                // [chunk][3][pstride] FP32 partial sums by slot
+    double eps2d;               // the same in FP64 (FP64 mode)
+    float* part;                // [group][3][pstride] FP32 partial sums by slot; the FP64
+                                // mode writes chunk c's sum as hi in group c, lo in c + S
     uint32_t pstride;
 };
 
@@ -90,7 +92,9 @@ struct StepArgs {
     int32_t* misc;              // [0] non-finite flag, [1] step after the last busy one
 };
 
-hipError_t launch_field(const FieldArgs& a, int tpt, uint32_t n_items, hipStream_t s);
+// precision: a GCCD_PRECISION_* mode
+hipError_t launch_field(const FieldArgs& a, int tpt, int precision, uint32_t n_items,
+                        hipStream_t s);
 hipError_t launch_step(const StepArgs& a, uint32_t n_slots, hipStream_t s);
 hipError_t launch_load(double* z, int32_t* cstep, const uint32_t* ev_off, uint32_t* ev_of,
                        uint32_t n_events, uint32_t n, double thickness, double z_well,

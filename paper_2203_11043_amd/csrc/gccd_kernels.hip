@@ -7,6 +7,7 @@
 //   image_bin     -- 2D histogram of collected holes (Sec. V.A)
 // Several independent events (clouds) can share one launch; every kernel
 // keeps them apart through the per-event slot offsets.
+#include "gccd.h"
 #include "gccd_internal.h"
 
 #include <math.h>
@@ -120,17 +121,29 @@ __device__ __forceinline__ double wave_max(double v) {
 // 2e-6 of the sum of its term magnitudes plus the FP32 summation error.
 // Each tile's contributions are summed separately and then added to the
 // running sum (blocked summation).
+//
+// The other GCCD_PRECISION_* modes change the origin (one per event, or
+// none: absolute coordinates) or the difference formation (hi parts only,
+// or hi and lo for every pair); they exist to measure those choices.
 // ---------------------------------------------------------------------------
-template <int TPT, bool CHECK>
+// How the difference of a pair is formed from the FP32 parts hi, lo of the
+// origin-relative coordinates.
+enum : int {
+    kDiffHi = 0,    // hi parts only
+    kDiffNear = 1,  // hi parts; pairs closer than rc recomputed with the lo parts added
+    kDiffAll = 2    // hi and lo parts for every pair (double-single differences)
+};
+
+template <int TPT, int DIFF>
 __device__ __forceinline__ void pair_terms(const float* __restrict__ lxp,
                                            const float* __restrict__ lyp,
                                            const float* __restrict__ lzp, uint32_t k, float shx,
-                                           float shy, float shz, const float (&thx)[TPT],
-                                           const float (&thy)[TPT], const float (&thz)[TPT],
-                                           const float (&tlx)[TPT], const float (&tly)[TPT],
-                                           const float (&tlz)[TPT], float eps2, float rc2,
-                                           float (&ax)[TPT], float (&ay)[TPT],
-                                           float (&az)[TPT]) {
+                                           float shy, float shz, float slx, float sly, float slz,
+                                           const float (&thx)[TPT], const float (&thy)[TPT],
+                                           const float (&thz)[TPT], const float (&tlx)[TPT],
+                                           const float (&tly)[TPT], const float (&tlz)[TPT],
+                                           float eps2, float rc2, float (&ax)[TPT],
+                                           float (&ay)[TPT], float (&az)[TPT]) {
     float dx[TPT], dy[TPT], dz[TPT], r2[TPT];
     bool near = false;
 #pragma unroll
@@ -138,21 +151,26 @@ __device__ __forceinline__ void pair_terms(const float* __restrict__ lxp,
         dx[t] = thx[t] - shx;
         dy[t] = thy[t] - shy;
         dz[t] = thz[t] - shz;
+        if (DIFF == kDiffAll) {
+            dx[t] += tlx[t] - slx;
+            dy[t] += tly[t] - sly;
+            dz[t] += tlz[t] - slz;
+        }
         r2[t] = __builtin_fmaf(dx[t], dx[t], eps2);
         r2[t] = __builtin_fmaf(dy[t], dy[t], r2[t]);
         r2[t] = __builtin_fmaf(dz[t], dz[t], r2[t]);
-        if (CHECK) near |= r2[t] < rc2;
+        if (DIFF == kDiffNear) near |= r2[t] < rc2;
     }
-    if (CHECK && __builtin_expect(__ballot(near) != 0ull, 0)) {
+    if (DIFF == kDiffNear && __builtin_expect(__ballot(near) != 0ull, 0)) {
         // wave-uniform branch, taken only when some lane of the wave has a
         // close pair: add the lo parts to the differences of those pairs
-        const float slx = lxp[k], sly = lyp[k], slz = lzp[k];
+        const float nlx = lxp[k], nly = lyp[k], nlz = lzp[k];
 #pragma unroll
         for (int t = 0; t < TPT; ++t) {
             if (r2[t] < rc2) {
-                dx[t] += tlx[t] - slx;
-                dy[t] += tly[t] - sly;
-                dz[t] += tlz[t] - slz;
+                dx[t] += tlx[t] - nlx;
+                dy[t] += tly[t] - nly;
+                dz[t] += tlz[t] - nlz;
                 r2[t] = __builtin_fmaf(dx[t], dx[t], eps2);
                 r2[t] = __builtin_fmaf(dy[t], dy[t], r2[t]);
                 r2[t] = __builtin_fmaf(dz[t], dz[t], r2[t]);
@@ -172,7 +190,7 @@ __device__ __forceinline__ void pair_terms(const float* __restrict__ lxp,
 }
 
 // All pairs of one staged tile (cnt sources) with the lane's TPT targets.
-template <int TPT, bool CHECK>
+template <int TPT, int DIFF>
 __device__ __forceinline__ void tile_terms(const float* __restrict__ hxp,
                                            const float* __restrict__ hyp,
                                            const float* __restrict__ hzp,
@@ -189,25 +207,32 @@ __device__ __forceinline__ void tile_terms(const float* __restrict__ hxp,
         const float4 hx4 = *reinterpret_cast<const float4*>(hxp + k);
         const float4 hy4 = *reinterpret_cast<const float4*>(hyp + k);
         const float4 hz4 = *reinterpret_cast<const float4*>(hzp + k);
-        pair_terms<TPT, CHECK>(lxp, lyp, lzp, k + 0, hx4.x, hy4.x, hz4.x, thx, thy, thz, tlx, tly,
-                               tlz, eps2, rc2, bx, by, bz);
-        pair_terms<TPT, CHECK>(lxp, lyp, lzp, k + 1, hx4.y, hy4.y, hz4.y, thx, thy, thz, tlx, tly,
-                               tlz, eps2, rc2, bx, by, bz);
-        pair_terms<TPT, CHECK>(lxp, lyp, lzp, k + 2, hx4.z, hy4.z, hz4.z, thx, thy, thz, tlx, tly,
-                               tlz, eps2, rc2, bx, by, bz);
-        pair_terms<TPT, CHECK>(lxp, lyp, lzp, k + 3, hx4.w, hy4.w, hz4.w, thx, thy, thz, tlx, tly,
-                               tlz, eps2, rc2, bx, by, bz);
+        float4 lx4 = make_float4(0.f, 0.f, 0.f, 0.f), ly4 = lx4, lz4 = lx4;
+        if (DIFF == kDiffAll) {
+            lx4 = *reinterpret_cast<const float4*>(lxp + k);
+            ly4 = *reinterpret_cast<const float4*>(lyp + k);
+            lz4 = *reinterpret_cast<const float4*>(lzp + k);
+        }
+        pair_terms<TPT, DIFF>(lxp, lyp, lzp, k + 0, hx4.x, hy4.x, hz4.x, lx4.x, ly4.x, lz4.x, thx,
+                              thy, thz, tlx, tly, tlz, eps2, rc2, bx, by, bz);
+        pair_terms<TPT, DIFF>(lxp, lyp, lzp, k + 1, hx4.y, hy4.y, hz4.y, lx4.y, ly4.y, lz4.y, thx,
+                              thy, thz, tlx, tly, tlz, eps2, rc2, bx, by, bz);
+        pair_terms<TPT, DIFF>(lxp, lyp, lzp, k + 2, hx4.z, hy4.z, hz4.z, lx4.z, ly4.z, lz4.z, thx,
+                              thy, thz, tlx, tly, tlz, eps2, rc2, bx, by, bz);
+        pair_terms<TPT, DIFF>(lxp, lyp, lzp, k + 3, hx4.w, hy4.w, hz4.w, lx4.w, ly4.w, lz4.w, thx,
+                              thy, thz, tlx, tly, tlz, eps2, rc2, bx, by, bz);
     }
     for (; k < cnt; ++k) {
-        pair_terms<TPT, CHECK>(lxp, lyp, lzp, k, hxp[k], hyp[k], hzp[k], thx, thy, thz, tlx, tly,
-                               tlz, eps2, rc2, bx, by, bz);
+        pair_terms<TPT, DIFF>(lxp, lyp, lzp, k, hxp[k], hyp[k], hzp[k], lxp[k], lyp[k], lzp[k], thx,
+                              thy, thz, tlx, tly, tlz, eps2, rc2, bx, by, bz);
     }
 }
 
-template <int TPT>
+template <int TPT, int PREC>
 __global__ __launch_bounds__(kFieldThreads) void field_tiles(FieldArgs a) {
     __shared__ __align__(16) float sh[2][6][kTile];
     __shared__ double box[6][kFieldThreads / 64];
+    __shared__ double ebox[6][kFieldThreads / 64];  // EVENT mode: the event's source box
     __shared__ double tbox[2][6];  // bounding box of the staged source tile
 
     const FieldItem it = a.items[blockIdx.x];
@@ -285,7 +310,43 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles(FieldArgs a) {
     hi_z = uniform(hi_z);
     // Every lane now holds the same box.  A box of non-finite positions
     // gives a NaN origin; the field is then NaN, and the step kernel flags it.
-    const double ox = 0.5 * (lo_x + hi_x), oy = 0.5 * (lo_y + hi_y), oz = 0.5 * (lo_z + hi_z);
+    double ox = 0.5 * (lo_x + hi_x), oy = 0.5 * (lo_y + hi_y), oz = 0.5 * (lo_z + hi_z);
+    if (PREC == GCCD_PRECISION_ABSOLUTE) {
+        ox = oy = oz = 0.0;
+    } else if (PREC == GCCD_PRECISION_EVENT) {
+        // centre of the union of the event's source-tile boxes
+        double e[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+        for (uint32_t t = (uint32_t)tid; t < ntiles; t += kFieldThreads) {
+            const size_t g = (size_t)tile0 + t;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                e[d] = fmin(e[d], a.tile_box[(size_t)d * a.tile_stride + g]);
+                e[d + 3] = fmax(e[d + 3], a.tile_box[(size_t)(d + 3) * a.tile_stride + g]);
+            }
+        }
+        const int wave = tid >> 6;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            e[d] = wave_min(e[d]);
+            e[d + 3] = wave_max(e[d + 3]);
+        }
+        if ((tid & 63) == 0) {
+#pragma unroll
+            for (int d = 0; d < 6; ++d) ebox[d][wave] = e[d];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < kFieldThreads / 64; ++w) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                e[d] = fmin(e[d], ebox[d][w]);
+                e[d + 3] = fmax(e[d + 3], ebox[d + 3][w]);
+            }
+        }
+        ox = uniform(0.5 * (e[0] + e[3]));
+        oy = uniform(0.5 * (e[1] + e[4]));
+        oz = uniform(0.5 * (e[2] + e[5]));
+    }
     const double hx = 0.5 * (hi_x - lo_x), hy = 0.5 * (hi_y - lo_y), hz = 0.5 * (hi_z - lo_z);
     const double rc2d = 0.0625 * (hx * hx + hy * hy + hz * hz);  // (rho / 4)^2
     const float rc2 = uniform((float)rc2d);
@@ -360,12 +421,15 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles(FieldArgs a) {
         const double gy = fmax(0.0, fmax(tb[1] - hi_y, lo_y - tb[4]));
         const double gz = fmax(0.0, fmax(tb[2] - hi_z, lo_z - tb[5]));
         const bool far_tile = gx * gx + gy * gy + gz * gz >= rc2d;
-        if (far_tile) {
-            tile_terms<TPT, false>(hxp, hyp, hzp, lxp, lyp, lzp, cnt, thx, thy, thz, tlx, tly, tlz,
-                                   a.eps2, rc2, bx, by, bz);
+        if (PREC == GCCD_PRECISION_COMPENSATED) {
+            tile_terms<TPT, kDiffAll>(hxp, hyp, hzp, lxp, lyp, lzp, cnt, thx, thy, thz, tlx, tly,
+                                      tlz, a.eps2, rc2, bx, by, bz);
+        } else if (PREC != GCCD_PRECISION_DEFAULT || far_tile) {
+            tile_terms<TPT, kDiffHi>(hxp, hyp, hzp, lxp, lyp, lzp, cnt, thx, thy, thz, tlx, tly,
+                                     tlz, a.eps2, rc2, bx, by, bz);
         } else {
-            tile_terms<TPT, true>(hxp, hyp, hzp, lxp, lyp, lzp, cnt, thx, thy, thz, tlx, tly, tlz,
-                                  a.eps2, rc2, bx, by, bz);
+            tile_terms<TPT, kDiffNear>(hxp, hyp, hzp, lxp, lyp, lzp, cnt, thx, thy, thz, tlx, tly,
+                                       tlz, a.eps2, rc2, bx, by, bz);
         }
 #pragma unroll
         for (int u = 0; u < TPT; ++u) {
@@ -392,15 +456,138 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles(FieldArgs a) {
     }
 }
 
-hipError_t launch_field(const FieldArgs& a, int tpt, uint32_t n_items, hipStream_t s) {
-    if (n_items == 0) return hipSuccess;
+// Eq. (6) entirely in FP64: the difference, r^2 + eps^2, r^-3 = 1/(q sqrt q)
+// with IEEE square root and division, and the sums.  Same work items, tiles
+// and source dealing as field_tiles; chunk c's FP64 sum is written as the
+// FP32 pair hi (group c) and lo (group c + S), which the FP64 reduction of
+// the groups adds back exactly.
+template <int TPT>
+__global__ __launch_bounds__(kFieldThreads) void field_tiles_f64(FieldArgs a) {
+    __shared__ double sh[2][3][kTile];
+
+    const FieldItem it = a.items[blockIdx.x];
+    const uint32_t off = a.ev_off[it.event];
+    const uint32_t ne = a.ev_off[it.event + 1] - off;
+    const uint32_t na = a.ev_active[it.event];
+    const uint32_t nt = a.targets_all ? ne : na;
+    const uint32_t ns = a.sources_all ? ne : na;
+    const uint32_t tbase = it.blk * (uint32_t)(kFieldThreads * TPT);
+    if (tbase >= nt) return;
+    const uint32_t ntiles = (ns + kTile - 1) / kTile;
+    const uint32_t chunk = it.chunk;
+    const uint32_t step_t = it.nchunk;
+    const int tid = threadIdx.x;
+    const double eps2 = a.eps2d;
+
+    double px[TPT], py[TPT], pz[TPT], ax[TPT], ay[TPT], az[TPT];
+#pragma unroll
+    for (int t = 0; t < TPT; ++t) {
+        const uint32_t ts = tbase + (uint32_t)(t * kFieldThreads + tid);
+        px[t] = py[t] = pz[t] = 0.0;
+        if (ts < nt) {
+            px[t] = a.px[off + ts];
+            py[t] = a.py[off + ts];
+            pz[t] = a.pz[off + ts];
+        }
+        ax[t] = ay[t] = az[t] = 0.0;
+    }
+
+    double qx = 0.0, qy = 0.0, qz = 0.0;
+    auto fetch = [&](uint32_t t) {
+        const uint32_t i = t * kTile + (uint32_t)tid;
+        qx = qy = qz = 0.0;
+        if (i < ns) {
+            qx = a.px[off + i];
+            qy = a.py[off + i];
+            qz = a.pz[off + i];
+        }
+    };
+    auto stage = [&](int b) {
+        sh[b][0][tid] = qx;
+        sh[b][1][tid] = qy;
+        sh[b][2][tid] = qz;
+    };
+
+    int buf = 0;
+    if (chunk < ntiles) {
+        fetch(chunk);
+        stage(0);
+    }
+    __syncthreads();
+    for (uint32_t t = chunk; t < ntiles; t += step_t) {
+        const uint32_t next = t + step_t;
+        if (next < ntiles) fetch(next);
+        const uint32_t cnt = min((uint32_t)kTile, ns - t * kTile);
+        for (uint32_t k = 0; k < cnt; ++k) {
+            const double sx = sh[buf][0][k], sy = sh[buf][1][k], sz = sh[buf][2][k];
+#pragma unroll
+            for (int u = 0; u < TPT; ++u) {
+                const double dx = px[u] - sx, dy = py[u] - sy, dz = pz[u] - sz;
+                double q = fma(dx, dx, eps2);
+                q = fma(dy, dy, q);
+                q = fma(dz, dz, q);
+                const double w = 1.0 / (q * sqrt(q));
+                ax[u] = fma(dx, w, ax[u]);
+                ay[u] = fma(dy, w, ay[u]);
+                az[u] = fma(dz, w, az[u]);
+            }
+        }
+        if (next < ntiles) stage(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+
+#pragma unroll
+    for (int t = 0; t < TPT; ++t) {
+        const uint32_t ts = tbase + (uint32_t)(t * kFieldThreads + tid);
+        if (ts >= nt) continue;
+        const double v[3] = {ax[t], ay[t], az[t]};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const float hi = (float)v[d];
+            const float lo = (float)(v[d] - (double)hi);
+            a.part[(size_t)(chunk * 3 + d) * a.pstride + off + ts] = hi;
+            a.part[(size_t)((step_t + chunk) * 3 + d) * a.pstride + off + ts] = lo;
+        }
+    }
+}
+
+template <int PREC>
+static hipError_t launch_field_prec(const FieldArgs& a, int tpt, uint32_t n_items,
+                                    hipStream_t s) {
     switch (tpt) {
-        case 1: field_tiles<1><<<n_items, kFieldThreads, 0, s>>>(a); break;
-        case 2: field_tiles<2><<<n_items, kFieldThreads, 0, s>>>(a); break;
-        case 4: field_tiles<4><<<n_items, kFieldThreads, 0, s>>>(a); break;
+        case 1: field_tiles<1, PREC><<<n_items, kFieldThreads, 0, s>>>(a); break;
+        case 2: field_tiles<2, PREC><<<n_items, kFieldThreads, 0, s>>>(a); break;
+        case 4: field_tiles<4, PREC><<<n_items, kFieldThreads, 0, s>>>(a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_field(const FieldArgs& a, int tpt, int precision, uint32_t n_items,
+                        hipStream_t s) {
+    if (n_items == 0) return hipSuccess;
+    switch (precision) {
+        case GCCD_PRECISION_DEFAULT:
+            return launch_field_prec<GCCD_PRECISION_DEFAULT>(a, tpt, n_items, s);
+        case GCCD_PRECISION_BLOCK:
+            return launch_field_prec<GCCD_PRECISION_BLOCK>(a, tpt, n_items, s);
+        case GCCD_PRECISION_EVENT:
+            return launch_field_prec<GCCD_PRECISION_EVENT>(a, tpt, n_items, s);
+        case GCCD_PRECISION_ABSOLUTE:
+            return launch_field_prec<GCCD_PRECISION_ABSOLUTE>(a, tpt, n_items, s);
+        case GCCD_PRECISION_COMPENSATED:
+            return launch_field_prec<GCCD_PRECISION_COMPENSATED>(a, tpt, n_items, s);
+        case GCCD_PRECISION_FP64:
+            switch (tpt) {
+                case 1: field_tiles_f64<1><<<n_items, kFieldThreads, 0, s>>>(a); break;
+                case 2: field_tiles_f64<2><<<n_items, kFieldThreads, 0, s>>>(a); break;
+                case 4: field_tiles_f64<4><<<n_items, kFieldThreads, 0, s>>>(a); break;
+                default: return hipErrorInvalidValue;
+            }
+            return hipGetLastError();
+        default: return hipErrorInvalidValue;
+    }
 }
 
 static uint32_t grid_for(uint64_t n, int threads, uint32_t cap) {

@@ -23,11 +23,21 @@ GCCD_E_DEVICE = -3
 GCCD_E_NOMEM = -4
 GCCD_E_NONFINITE = -5
 
+# arithmetic of the Eq. (6) kernel (gccd_set_precision)
+GCCD_PRECISION_DEFAULT = 0
+GCCD_PRECISION_BLOCK = 1
+GCCD_PRECISION_EVENT = 2
+GCCD_PRECISION_ABSOLUTE = 3
+GCCD_PRECISION_COMPENSATED = 4
+GCCD_PRECISION_FP64 = 5
+PRECISION_MODES = {"default": 0, "block": 1, "event": 2, "absolute": 3, "compensated": 4,
+                   "fp64": 5}
+
 # every symbol the header declares
 EXPORTS = ("gccd_init", "gccd_load", "gccd_load_events", "gccd_run", "gccd_image",
            "gccd_image_events", "gccd_field", "gccd_positions", "gccd_stats",
-           "gccd_set_launch", "gccd_set_timing", "gccd_strerror", "gccd_last_error",
-           "gccd_destroy")
+           "gccd_set_launch", "gccd_set_precision", "gccd_set_timing", "gccd_strerror",
+           "gccd_last_error", "gccd_destroy")
 
 
 class CParams(ctypes.Structure):
@@ -83,6 +93,7 @@ def _load():
     L.gccd_positions.argtypes = [P, P, P, P, P]
     L.gccd_stats.argtypes = [P, ctypes.POINTER(CStats)]
     L.gccd_set_launch.argtypes = [P, i32, i32]
+    L.gccd_set_precision.argtypes = [P, i32]
     L.gccd_set_timing.argtypes = [P, i32]
     L.gccd_strerror.argtypes = [ctypes.c_int]
     L.gccd_strerror.restype = ctypes.c_char_p
@@ -242,6 +253,12 @@ def gccd_stats(ctx: int) -> dict:
 
 def gccd_set_launch(ctx: int, targets_per_thread: int = 0, source_chunks: int = 0) -> None:
     _check(ctx, lib.gccd_set_launch(ctx, int(targets_per_thread), int(source_chunks)))
+
+
+def gccd_set_precision(ctx: int, mode) -> None:
+    """mode: a GCCD_PRECISION_* value or its name ("default", "fp64", ...)."""
+    m = PRECISION_MODES[mode] if isinstance(mode, str) else int(mode)
+    _check(ctx, lib.gccd_set_precision(ctx, m))
 
 
 def gccd_set_timing(ctx: int, on: bool) -> None:

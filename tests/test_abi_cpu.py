@@ -29,7 +29,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported(g):
     names = declared_functions()
-    assert len(names) == 14
+    assert len(names) == 15
     for name in names:
         assert hasattr(g.lib, name), name
     assert sorted(g.EXPORTS) == names
@@ -104,6 +104,7 @@ def test_null_arguments(g):
     assert L.gccd_stats(None, None) == g.GCCD_E_INVALID
     assert L.gccd_set_launch(None, 0, 0) == g.GCCD_E_INVALID
     assert L.gccd_set_timing(None, 1) == g.GCCD_E_INVALID
+    assert L.gccd_set_precision(None, 0) == g.GCCD_E_INVALID
     L.gccd_destroy(None)
     assert L.gccd_last_error(None) == b""
 
