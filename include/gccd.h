@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define GCCD_ABI_VERSION 1u
+#define GCCD_ABI_VERSION 2u
 
 enum {
     GCCD_OK = 0,
@@ -84,6 +84,8 @@ typedef struct {
     int32_t source_chunks;     /* source chunks of event 0's field sum               */
     int64_t n_events;          /* events loaded                                       */
     int64_t max_source_chunks; /* largest source split over all events               */
+    int64_t closure_steps;     /* steps whose Coulomb field came from the closure     */
+    int64_t near_chunks;       /* source chunks of the closure's near sum (last run)  */
 } gccd_stats_t;
 
 /* Creates a context bound to the current HIP device and to hip_stream (a
@@ -208,6 +210,52 @@ enum {
  * larger gccd_set_launch value is clamped).  Applies to the current load and
  * later ones; synchronises the stream.  GCCD_E_INVALID for an unknown mode. */
 int gccd_set_precision(gccd_ctx* c, int32_t mode);
+
+/* Far-field closure.  The Eq. (6) sum is split at a distance a: sources
+ * closer than a are summed exactly, pair by pair, as in the exact path; the
+ * rest is read from a grid.  Every carrier (travelling or collected) deposits
+ * its charge with trilinear weights on a 32^3 grid of spacing h centred on
+ * the charges' centroid, h = max(0.5 s, d_max / 14) with s the rms width per
+ * axis and d_max the largest offset of a charge from the centroid on any
+ * axis; a = 0.8 h.  A linear U-Net maps the grid charge to the far field at
+ * the nodes in units of K / h^2 (K of Eq. (6)), evaluated in bf16 on the
+ * matrix cores with FP32 accumulation, and Catmull-Rom interpolation carries
+ * it to the carriers.  The paper computes the full O(N^2) sum; the closure is
+ * an approximation for large single clouds, trained on exact fields.
+ *
+ * The network: convolutions without bias, PyTorch Conv3d weight layout
+ * (c_out, c_in, kz, ky, kx), in this order (name: c_in -> c_out, grid):
+ *   e0a 1->16, e0b 16->16 (32^3); 2x2x2 mean; e1a 16->32, e1b 32->32 (16^3);
+ *   mean; e2a 32->32, e2b 32->32 (8^3); mean; b3a 32->32, b3b 32->32 (4^3);
+ *   x2 linear upsampling of b3b, joined with e2b -> d2 64->32 (8^3);
+ *   upsampled d2 with e1b -> d1 64->32 (16^3); upsampled d1 with e0b ->
+ *   d0 48->16 (32^3); head 16->3, 1x1x1 (32^3).  3x3x3 kernels with zero
+ *   padding except the head; the joined tensors hold the upsampled channels
+ *   first.  GCCD_CLOSURE_WEIGHTS floats in all. */
+#define GCCD_CLOSURE_WEIGHTS 290784
+
+/* Enables the closure for gccd_run and gccd_field when the load is a single
+ * event of at least min_carriers holes with Coulomb repulsion on and
+ * collected holes kept as sources; any other load uses the exact path (the
+ * fallback).  weights is a HOST array of n_weights = GCCD_CLOSURE_WEIGHTS
+ * FP32 values (copied and rounded to bf16); NULL disables the closure.
+ * Synchronises the stream.  GCCD_E_INVALID for a wrong count, a negative
+ * min_carriers or non-finite weights; GCCD_E_NOMEM if the grid buffers
+ * cannot be allocated. */
+int gccd_set_closure(gccd_ctx* c, const float* weights, int64_t n_weights,
+                     int64_t min_carriers);
+
+/* The closure's two parts at every loaded carrier, from the current
+ * positions, whether or not the closure is enabled: near_* receives the exact
+ * sum over the sources closer than a and far_* the interpolated far field
+ * (zero when no weights are set), both in V/cm, carrier order, device arrays
+ * of n doubles; rho (device, 32^3 floats, index (z * 32 + y) * 32 + x) the
+ * deposited charge per node; grid (device, 4 doubles) the position of node 0
+ * and the spacing h in um.  Uses the single event of the load.  Synchronises
+ * the stream.  GCCD_E_STATE before load or with more than one event,
+ * GCCD_E_INVALID for NULL pointers. */
+int gccd_closure_parts(gccd_ctx* c, double* near_x, double* near_y, double* near_z,
+                       double* far_x, double* far_y, double* far_z, float* rho, double* grid);
 
 /* on = 1 times every Eq. (6) launch with HIP events on the context's stream
  * (reported by gccd_stats); on = 0 stops timing. */

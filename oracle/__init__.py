@@ -83,6 +83,7 @@ def lib():
         L.orc_thermal_voltage.argtypes = [d]
         L.orc_thermal_voltage.restype = d
         L.orc_field.argtypes = [i64, P, P, P, i64, P, P, P, d, d, P, P, P, P]
+        L.orc_field_window.argtypes = [i64, P, P, P, i64, P, P, P, d, d, d, d, P, P, P]
         L.orc_prepare.argtypes = [P, i64, P, P, P, P]
         L.orc_prepare.restype = i64
         L.orc_run.argtypes = [P, d, i64, P, P, P, P, i64, i64, P, P]
@@ -172,6 +173,19 @@ def field(targets, sources=None, softening_um: float = 1e-3, eps_r: float = 11.7
                     _ptr(E[0]), _ptr(E[1]), _ptr(E[2]),
                     _ptr(A) if A is not None else None)
     return (E, A) if with_magnitude else E
+
+
+def field_window(targets, sources, r_lo: float, r_hi: float, softening_um: float = 1e-3,
+                 eps_r: float = 11.7):
+    """Eq. (6) at the targets from the sources at distance r_lo <= r < r_hi."""
+    t = [_f64(v) for v in targets]
+    s = [_f64(v) for v in sources]
+    E = np.zeros((3, t[0].size), dtype=np.float64)
+    lib().orc_field_window(t[0].size, _ptr(t[0]), _ptr(t[1]), _ptr(t[2]), s[0].size,
+                           _ptr(s[0]), _ptr(s[1]), _ptr(s[2]), softening_um,
+                           coulomb_constant(eps_r), float(r_lo), float(r_hi),
+                           _ptr(E[0]), _ptr(E[1]), _ptr(E[2]))
+    return E
 
 
 class State:

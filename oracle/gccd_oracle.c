@@ -148,6 +148,34 @@ void orc_field(int64_t nt, const double* tx, const double* ty, const double* tz,
     }
 }
 
+/* Eq. (6) restricted to the sources whose distance r = |r_ij| from the target
+ * lies in [r_lo, r_hi): the split of the sum that a near-field/far-field
+ * scheme uses.  Same term as orc_field; distances compared unsoftened. */
+void orc_field_window(int64_t nt, const double* tx, const double* ty, const double* tz,
+                      int64_t ns, const double* sx, const double* sy, const double* sz,
+                      double softening_um, double K, double r_lo, double r_hi,
+                      double* ex, double* ey, double* ez) {
+    double soft2 = softening_um * softening_um;
+    double lo2 = r_lo * r_lo, hi2 = r_hi * r_hi;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t j = 0; j < nt; ++j) {
+        double acc_x = 0.0, acc_y = 0.0, acc_z = 0.0;
+        for (int64_t i = 0; i < ns; ++i) {
+            double ux = tx[j] - sx[i], uy = ty[j] - sy[i], uz = tz[j] - sz[i];
+            double dist2 = ux * ux + uy * uy + uz * uz;
+            if (dist2 < lo2 || !(dist2 < hi2)) continue;
+            double s = dist2 + soft2;
+            double inv3 = 1.0 / (s * sqrt(s));
+            acc_x += ux * inv3;
+            acc_y += uy * inv3;
+            acc_z += uz * inv3;
+        }
+        ex[j] = K * acc_x;
+        ey[j] = K * acc_y;
+        ez[j] = K * acc_z;
+    }
+}
+
 /* ---- load-time boundary handling ------------------------------------------ */
 int64_t orc_prepare(const orc_params* p, int64_t n, double* x, double* y, double* z,
                     int32_t* cstep) {

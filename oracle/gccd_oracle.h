@@ -62,6 +62,13 @@ void orc_field(int64_t nt, const double* tx, const double* ty, const double* tz,
                double softening_um, double K,
                double* ex, double* ey, double* ez, double* amag);
 
+/* Eq. (6) over the sources at distance r_lo <= |r_ij| < r_hi from each target
+ * (r_hi may be INFINITY).  Used to check a near-field/far-field split. */
+void orc_field_window(int64_t nt, const double* tx, const double* ty, const double* tz,
+                      int64_t ns, const double* sx, const double* sy, const double* sz,
+                      double softening_um, double K, double r_lo, double r_hi,
+                      double* ex, double* ey, double* ez);
+
 /* Load-time boundary handling: z above the back surface is mirrored back into
  * the bulk; z at or below the well is collected at step 0 (cstep = 0); every
  * other carrier is active (cstep = -1).  Returns the number of active ones. */

@@ -14,6 +14,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libgccd.so")
 SOURCES = [os.path.join(HERE, "csrc", "gccd_api.hip"),
            os.path.join(HERE, "csrc", "gccd_sort.hip"),
+           os.path.join(HERE, "csrc", "gccd_closure.hip"),
            os.path.join(HERE, "csrc", "gccd_kernels.hip")]
 ARCH = os.environ.get("GCCD_OFFLOAD_ARCH", "gfx950")
 

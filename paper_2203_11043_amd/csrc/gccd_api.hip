@@ -98,6 +98,23 @@ struct gccd_ctx {
     int tpt = 1;
     int precision = GCCD_PRECISION_DEFAULT;
 
+    // far-field closure (load-independent buffers)
+    bool closure_on = false;
+    int64_t closure_min = 0;
+    uint16_t* wpk = nullptr;           // packed bf16 weights of every layer
+    std::vector<size_t> wpk_off;       // offset of each layer in wpk (elements)
+    uint16_t* act = nullptr;           // every bf16 activation buffer of the network
+    float* fgrid = nullptr;            // far field at the nodes [32^3][4]
+    float* rho_f32 = nullptr;          // deposited charge [32^3]
+    unsigned long long* acc = nullptr; // fixed-point deposit [32^3]
+    GridParams* gp = nullptr;
+    double* mom = nullptr;             // [kMomBlocks][10]
+    int part_groups = 0;               // capacity of part, in groups
+    int near_chunks = 1;
+    int groups_mode = 0;               // what ev_chunks_d holds: 0 exact groups, 1 closure
+    int32_t closure_groups = 1;        // host copy of the closure's group count
+    int64_t closure_steps = 0;
+
     bool timing = false;
     std::vector<hipEvent_t> ev;
     int ev_used = 0;
@@ -178,8 +195,20 @@ void free_buffers(gccd_ctx* c) {
     hfree(c->host_active);
     hfree(c->host_items);
     c->items_cap = 0;
+    c->part_groups = 0;
     c->sort_tmp_bytes = 0;
     c->loaded = false;
+}
+
+void free_closure(gccd_ctx* c) {
+    dfree(c->wpk);
+    dfree(c->act);
+    dfree(c->fgrid);
+    dfree(c->rho_f32);
+    dfree(c->acc);
+    dfree(c->gp);
+    dfree(c->mom);
+    c->closure_on = false;
 }
 
 uint32_t bits_for(uint64_t count) {  // smallest b with 2^b >= count (0 for count <= 1)
@@ -259,6 +288,8 @@ int size_chunk_buffers(gccd_ctx* c) {
         items += (size_t)((ne + kFieldThreads - 1) / kFieldThreads) * (size_t)c->chunks_h[e];
     }
     c->items_cap = std::max<size_t>(items, 1);
+    c->part_groups = c->max_groups;
+    c->groups_mode = 0;
     if (hipMalloc(&c->part, (size_t)c->max_groups * 3 * (size_t)c->n * sizeof(float)) !=
             hipSuccess ||
         hipMalloc(&c->items_d, c->items_cap * sizeof(FieldItem)) != hipSuccess ||
@@ -355,6 +386,199 @@ int read_counts(gccd_ctx* c) {
     return GCCD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Far-field closure: network description, buffers, the field sequence.
+// ---------------------------------------------------------------------------
+struct LayerDesc {
+    int cin, cout, taps;
+};
+// in the order of the weight array (the header lists the names)
+constexpr LayerDesc kLayers[12] = {{1, 16, 27},  {16, 16, 27}, {16, 32, 27}, {32, 32, 27},
+                                   {32, 32, 27}, {32, 32, 27}, {32, 32, 27}, {32, 32, 27},
+                                   {64, 32, 27}, {64, 32, 27}, {48, 16, 27}, {16, 3, 1}};
+enum : int { kE0a, kE0b, kE1a, kE1b, kE2a, kE2b, kB3a, kB3b, kD2, kD1, kD0, kHead };
+
+// bf16 activation tensors, channels last: (nodes per axis, channels)
+enum : int { kX0, kT0, kD0b, kP1, kT1, kD1b, kP2, kT2, kD2b, kP3, kT3, kB3, kE2, kE1, kE0, kNumAct };
+constexpr int kActN[kNumAct] = {32, 32, 32, 16, 16, 16, 8, 8, 8, 4, 4, 4, 8, 16, 32};
+constexpr int kActC[kNumAct] = {1, 16, 48, 16, 32, 64, 32, 32, 64, 32, 32, 32, 32, 32, 16};
+
+size_t act_offset(int t) {
+    size_t o = 0;
+    for (int i = 0; i < t; ++i) o += (size_t)kActN[i] * kActN[i] * kActN[i] * kActC[i];
+    return o;
+}
+
+uint16_t host_bf16(float f) {  // round to nearest, ties to even
+    uint32_t b;
+    memcpy(&b, &f, 4);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return (uint16_t)(b >> 16);
+}
+
+int ensure_closure_buffers(gccd_ctx* c) {
+    if (c->act) return GCCD_OK;
+    const size_t act = act_offset(kNumAct);
+    if (hipMalloc(&c->act, act * sizeof(uint16_t)) != hipSuccess ||
+        hipMalloc(&c->fgrid, (size_t)kGridNodes * 4 * sizeof(float)) != hipSuccess ||
+        hipMalloc(&c->rho_f32, (size_t)kGridNodes * sizeof(float)) != hipSuccess ||
+        hipMalloc(&c->acc, (size_t)kGridNodes * sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc(&c->gp, sizeof(GridParams)) != hipSuccess ||
+        hipMalloc(&c->mom, (size_t)kMomBlocks * 10 * sizeof(double)) != hipSuccess) {
+        free_closure(c);
+        return fail(c, GCCD_E_NOMEM, "closure buffer allocation failed");
+    }
+    GCCD_HIP(c, launch_fill_u32(reinterpret_cast<uint32_t*>(c->fgrid), (uint64_t)kGridNodes * 4,
+                                0u, c->stream));
+    return GCCD_OK;
+}
+
+bool closure_applies(const gccd_ctx* c) {
+    return c->closure_on && c->loaded && c->list_mode && c->n_events == 1 &&
+           c->p.collected_are_sources && c->n >= c->closure_min;
+}
+
+// Source chunks of the near sum: enough workgroups to fill the chip, at least
+// 4 candidate tiles per chunk, at most 32.
+void choose_near_chunks(gccd_ctx* c) {
+    const uint64_t blocks = ((uint64_t)c->n + kFieldThreads - 1) / kFieldThreads;
+    const uint64_t tiles = ((uint64_t)c->n + kTile - 1) / kTile;
+    uint64_t s = ((uint64_t)c->n_cu * 48 + blocks - 1) / blocks;
+    s = std::min<uint64_t>(s, std::max<uint64_t>(1, tiles / 4));
+    s = std::min<uint64_t>(s, 32);
+    c->near_chunks = (int)std::max<uint64_t>(s, 1);
+}
+
+// part holds the near chunks plus one group for the far field; the item
+// buffers hold every (target block, chunk) pair.
+int ensure_closure_capacity(gccd_ctx* c) {
+    const int groups = c->near_chunks + 1;
+    if (groups > c->part_groups) {
+        dfree(c->part);
+        if (hipMalloc(&c->part, (size_t)groups * 3 * (size_t)c->n * sizeof(float)) != hipSuccess)
+            return fail(c, GCCD_E_NOMEM, "closure partial-sum allocation failed");
+        c->part_groups = groups;
+    }
+    const size_t items = (((size_t)c->n + kFieldThreads - 1) / kFieldThreads) * c->near_chunks;
+    if (items > c->items_cap) {
+        dfree(c->items_d);
+        hfree(c->host_items);
+        if (hipMalloc(&c->items_d, items * sizeof(FieldItem)) != hipSuccess ||
+            hipHostMalloc((void**)&c->host_items, items * sizeof(FieldItem)) != hipSuccess)
+            return fail(c, GCCD_E_NOMEM, "closure work-item allocation failed");
+        c->items_cap = items;
+    }
+    return GCCD_OK;
+}
+
+int build_near_items(gccd_ctx* c, uint32_t bound) {
+    const uint32_t blocks = (bound + kFieldThreads - 1) / kFieldThreads;
+    const uint32_t s = (uint32_t)c->near_chunks;
+    size_t k = 0;
+    for (uint32_t b = 0; b < blocks; ++b)
+        for (uint32_t ch = 0; ch < s; ++ch) {
+            if (k >= c->items_cap) return fail(c, GCCD_E_DEVICE, "work item overflow");
+            c->host_items[k++] = FieldItem{0, b, ch, s};
+        }
+    c->n_items = (uint32_t)k;
+    if (k) {
+        GCCD_HIP(c, hipMemcpyAsync(c->items_d, c->host_items, k * sizeof(FieldItem),
+                                   hipMemcpyHostToDevice, c->stream));
+    }
+    return GCCD_OK;
+}
+
+// What the step kernel and gccd_field sum per event: the exact path's groups,
+// or the closure's near chunks plus the far group (single event).
+int set_groups(gccd_ctx* c, int mode) {
+    if (mode == c->groups_mode) return GCCD_OK;
+    if (mode == 1) {
+        c->closure_groups = c->near_chunks + 1;
+        GCCD_HIP(c, hipMemcpyAsync(c->ev_chunks_d, &c->closure_groups, sizeof(int32_t),
+                                   hipMemcpyHostToDevice, c->stream));
+    } else {
+        GCCD_HIP(c, hipMemcpyAsync(c->ev_chunks_d, c->groups_h.data(),
+                                   c->n_events * sizeof(int32_t), hipMemcpyHostToDevice,
+                                   c->stream));
+    }
+    GCCD_HIP(c, hipStreamSynchronize(c->stream));  // the host source may change next
+    c->groups_mode = mode;
+    return GCCD_OK;
+}
+
+int run_network(gccd_ctx* c) {
+    uint16_t* A = c->act;
+    auto T = [&](int t) { return A + act_offset(t); };
+    auto conv = [&](int layer, int in, int in_off, int out, int out_off) -> hipError_t {
+        const LayerDesc& L = kLayers[layer];
+        ConvArgs a{};
+        a.in = T(in);
+        a.in_stride = kActC[in];
+        a.in_off = in_off;
+        a.cin = L.cin;
+        a.wpk = c->wpk + c->wpk_off[layer];
+        a.nslice = (L.taps * L.cin + 31) / 32;
+        a.ntile = (L.cout + 15) / 16;
+        a.taps = L.taps;
+        a.n = kActN[in];
+        a.cout = L.cout;
+        if (out < 0) {
+            a.outf = c->fgrid;
+        } else {
+            a.out = T(out);
+            a.out_stride = kActC[out];
+            a.out_off = out_off;
+        }
+        return launch_conv(a, c->stream);
+    };
+    hipStream_t st = c->stream;
+    GCCD_HIP(c, conv(kE0a, kX0, 0, kT0, 0));
+    GCCD_HIP(c, conv(kE0b, kT0, 0, kD0b, 32));            // skip 0 -> channels 32..47
+    GCCD_HIP(c, launch_pool(T(kD0b), 48, 32, 16, 32, T(kP1), st));
+    GCCD_HIP(c, conv(kE1a, kP1, 0, kT1, 0));
+    GCCD_HIP(c, conv(kE1b, kT1, 0, kD1b, 32));            // skip 1 -> channels 32..63
+    GCCD_HIP(c, launch_pool(T(kD1b), 64, 32, 32, 16, T(kP2), st));
+    GCCD_HIP(c, conv(kE2a, kP2, 0, kT2, 0));
+    GCCD_HIP(c, conv(kE2b, kT2, 0, kD2b, 32));            // skip 2 -> channels 32..63
+    GCCD_HIP(c, launch_pool(T(kD2b), 64, 32, 32, 8, T(kP3), st));
+    GCCD_HIP(c, conv(kB3a, kP3, 0, kT3, 0));
+    GCCD_HIP(c, conv(kB3b, kT3, 0, kB3, 0));
+    GCCD_HIP(c, launch_upsample(T(kB3), 32, 4, T(kD2b), 64, 0, st));
+    GCCD_HIP(c, conv(kD2, kD2b, 0, kE2, 0));
+    GCCD_HIP(c, launch_upsample(T(kE2), 32, 8, T(kD1b), 64, 0, st));
+    GCCD_HIP(c, conv(kD1, kD1b, 0, kE1, 0));
+    GCCD_HIP(c, launch_upsample(T(kE1), 32, 16, T(kD0b), 48, 0, st));
+    GCCD_HIP(c, conv(kD0, kD0b, 0, kE0, 0));
+    GCCD_HIP(c, conv(kHead, kE0, 0, -1, 0));
+    return GCCD_OK;
+}
+
+// The closure's field of the current sorted list: near chunks into groups
+// [0, S), the far field of target slots [0, nt) into group S.
+int closure_field(gccd_ctx* c, bool targets_all, uint32_t nt, bool with_net) {
+    const uint32_t n = (uint32_t)c->n;
+    const double eps2 = c->p.softening_um * c->p.softening_um;
+    hipStream_t st = c->stream;
+    GCCD_HIP(c, launch_moments(c->ps[0], c->ps[1], c->ps[2], n, c->mom, st));
+    GCCD_HIP(c, launch_grid_params(c->mom, c->ps[0], c->ps[1], c->ps[2], n, eps2, c->gp, st));
+    GCCD_HIP(c, launch_fill_u32(reinterpret_cast<uint32_t*>(c->acc), 2ull * kGridNodes, 0u, st));
+    GCCD_HIP(c, launch_deposit(c->ps[0], c->ps[1], c->ps[2], n, c->gp, c->acc, st));
+    GCCD_HIP(c, launch_rho(c->acc, c->act + act_offset(kX0), c->rho_f32, st));
+    if (with_net) {
+        int r = run_network(c);
+        if (r != GCCD_OK) return r;
+    }
+    FieldArgs fa = field_args(c, targets_all);
+    GCCD_HIP(c, launch_near(fa, c->gp, c->n_items, st));
+    float* far = c->part + (size_t)c->near_chunks * 3 * n;
+    if (with_net)
+        GCCD_HIP(c, launch_far(c->fgrid, c->gp, c->ps[0], c->ps[1], c->ps[2], nt, far, far + n,
+                               far + 2 * (size_t)n, st));
+    else
+        GCCD_HIP(c, launch_fill_u32(reinterpret_cast<uint32_t*>(far), 3ull * n, 0u, st));
+    return GCCD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -419,6 +643,7 @@ void gccd_destroy(gccd_ctx* c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
     free_buffers(c);
+    free_closure(c);
     (void)hipFree(c->meta);
     (void)hipHostFree(c->host_meta);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
@@ -535,6 +760,7 @@ int gccd_load_events(gccd_ctx* c, int32_t n_events, const int64_t* offsets, cons
     c->field_ms = 0;
     c->field_launches = 0;
     c->ev_used = 0;
+    c->closure_steps = 0;
     return GCCD_OK;
 }
 
@@ -582,6 +808,93 @@ int gccd_set_precision(gccd_ctx* c, int32_t mode) {
     return GCCD_OK;
 }
 
+int gccd_set_closure(gccd_ctx* c, const float* weights, int64_t n_weights,
+                     int64_t min_carriers) {
+    if (!c) return GCCD_E_INVALID;
+    if (weights && (n_weights != GCCD_CLOSURE_WEIGHTS || min_carriers < 0))
+        return fail(c, GCCD_E_INVALID, "gccd_set_closure: wrong weight count or min_carriers");
+    if (weights) {
+        for (int64_t i = 0; i < n_weights; ++i)
+            if (!std::isfinite(weights[i]))
+                return fail(c, GCCD_E_INVALID, "gccd_set_closure: non-finite weight");
+    }
+    GCCD_HIP(c, hipStreamSynchronize(c->stream));
+    dfree(c->wpk);
+    c->closure_on = false;
+    if (!weights) return GCCD_OK;
+
+    // pack every layer in the B-operand order of the MFMA convolution
+    std::vector<uint16_t> packed;
+    c->wpk_off.clear();
+    size_t src = 0;
+    for (const LayerDesc& L : kLayers) {
+        const int kmax = L.taps * L.cin;
+        const int nslice = (kmax + 31) / 32, ntile = (L.cout + 15) / 16;
+        c->wpk_off.push_back(packed.size());
+        for (int s = 0; s < nslice; ++s)
+            for (int t = 0; t < ntile; ++t)
+                for (int l = 0; l < 64; ++l)
+                    for (int i = 0; i < 8; ++i) {
+                        const int k = s * 32 + (l >> 4) * 8 + i, co = t * 16 + (l & 15);
+                        float v = 0.0f;
+                        if (k < kmax && co < L.cout) {
+                            const int tap = k / L.cin, ci = k % L.cin;
+                            v = weights[src + ((size_t)co * L.cin + ci) * L.taps + tap];
+                        }
+                        packed.push_back(host_bf16(v));
+                    }
+        src += (size_t)L.cout * L.cin * L.taps;
+    }
+    if (src != (size_t)GCCD_CLOSURE_WEIGHTS)
+        return fail(c, GCCD_E_INVALID, "gccd_set_closure: layer table and weight count differ");
+    int r = ensure_closure_buffers(c);
+    if (r != GCCD_OK) return r;
+    if (hipMalloc(&c->wpk, packed.size() * sizeof(uint16_t)) != hipSuccess)
+        return fail(c, GCCD_E_NOMEM, "gccd_set_closure: weight allocation failed");
+    GCCD_HIP(c, hipMemcpyAsync(c->wpk, packed.data(), packed.size() * sizeof(uint16_t),
+                               hipMemcpyHostToDevice, c->stream));
+    GCCD_HIP(c, hipStreamSynchronize(c->stream));  // packed goes out of scope
+    c->closure_on = true;
+    c->closure_min = min_carriers;
+    return GCCD_OK;
+}
+
+int gccd_closure_parts(gccd_ctx* c, double* near_x, double* near_y, double* near_z,
+                       double* far_x, double* far_y, double* far_z, float* rho, double* grid) {
+    if (!c) return GCCD_E_INVALID;
+    if (!c->loaded) return fail(c, GCCD_E_STATE, "gccd_closure_parts before gccd_load");
+    if (c->n_events != 1)
+        return fail(c, GCCD_E_STATE, "gccd_closure_parts: the load has more than one event");
+    if (!near_x || !near_y || !near_z || !far_x || !far_y || !far_z || !rho || !grid)
+        return fail(c, GCCD_E_INVALID, "gccd_closure_parts: NULL pointer");
+    const uint32_t n = (uint32_t)c->n;
+    GCCD_HIP(c, hipStreamSynchronize(c->stream));
+    int r = ensure_closure_buffers(c);
+    if (r != GCCD_OK) return r;
+    if (!c->list_mode) {
+        GCCD_HIP(c, launch_make_keys(c->x, c->y, c->z, c->cstep, c->ev_of, c->ev_off_d, n, c->kl,
+                                     c->keys[c->cur ^ 1], c->stream));
+        r = finish_list(c);
+        if (r != GCCD_OK) return r;
+    }
+    choose_near_chunks(c);
+    r = ensure_closure_capacity(c);
+    if (r == GCCD_OK) r = build_near_items(c, n);
+    if (r == GCCD_OK) r = closure_field(c, true, n, c->wpk != nullptr);
+    if (r != GCCD_OK) return r;
+    const int S = c->near_chunks;
+    GCCD_HIP(c, launch_field_finish(c->part, n, c->ev_chunks_d, 0, S, c->keys[c->cur], c->ev_off_d,
+                                    c->kl, n, c->K, near_x, near_y, near_z, c->stream));
+    GCCD_HIP(c, launch_field_finish(c->part, n, c->ev_chunks_d, S, 1, c->keys[c->cur], c->ev_off_d,
+                                    c->kl, n, c->K, far_x, far_y, far_z, c->stream));
+    GCCD_HIP(c, hipMemcpyAsync(rho, c->rho_f32, (size_t)kGridNodes * sizeof(float),
+                               hipMemcpyDeviceToDevice, c->stream));
+    GCCD_HIP(c, hipMemcpyAsync(grid, c->gp, 4 * sizeof(double), hipMemcpyDeviceToDevice,
+                               c->stream));
+    GCCD_HIP(c, hipStreamSynchronize(c->stream));
+    return GCCD_OK;
+}
+
 int gccd_set_timing(gccd_ctx* c, int32_t on) {
     if (!c || (on | 1) != 1) return GCCD_E_INVALID;
     c->timing = on != 0;
@@ -601,8 +914,21 @@ int gccd_run(gccd_ctx* c, double dt_ps, int64_t max_steps, int64_t* steps_done,
     const uint32_t n = (uint32_t)c->n;
     int64_t bound = c->n_active;
     GCCD_HIP(c, hipStreamSynchronize(c->stream));  // the item staging buffer is free
+    const bool use_closure = closure_applies(c);
+    if (use_closure) {
+        choose_near_chunks(c);
+        int r = ensure_closure_capacity(c);
+        if (r == GCCD_OK) r = set_groups(c, 1);
+        if (r != GCCD_OK) return r;
+    } else if (c->list_mode) {
+        int r = set_groups(c, 0);
+        if (r != GCCD_OK) return r;
+    }
+    auto rebuild = [&]() -> int {
+        return use_closure ? build_near_items(c, (uint32_t)bound) : build_items(c, c->host_active);
+    };
     if (c->list_mode && bound > 0) {
-        int r = build_items(c, c->host_active);
+        int r = rebuild();
         if (r != GCCD_OK) return r;
     }
 
@@ -648,11 +974,16 @@ int gccd_run(gccd_ctx* c, double dt_ps, int64_t max_steps, int64_t* steps_done,
             const uint32_t s = (uint32_t)(step0 + k + i);
             sa.step = s;
             if (c->list_mode) {
-                FieldArgs fa = field_args(c, false);
                 hipEvent_t* evp = nullptr;
                 int r = record_field_start(c, &evp);
                 if (r != GCCD_OK) return r;
-                GCCD_HIP(c, launch_field(fa, c->tpt, c->precision, c->n_items, c->stream));
+                if (use_closure) {
+                    r = closure_field(c, false, (uint32_t)bound, true);
+                    if (r != GCCD_OK) return r;
+                } else {
+                    FieldArgs fa = field_args(c, false);
+                    GCCD_HIP(c, launch_field(fa, c->tpt, c->precision, c->n_items, c->stream));
+                }
                 if (evp) GCCD_HIP(c, hipEventRecord(evp[1], c->stream));
                 sa.keys_in = c->keys[c->cur];
                 sa.keys_out = c->keys[c->cur ^ 1];
@@ -685,7 +1016,7 @@ int gccd_run(gccd_ctx* c, double dt_ps, int64_t max_steps, int64_t* steps_done,
                         "gccd_run: a carrier position became non-finite; reload to continue");
         }
         if (c->list_mode && bound > 0 && k < max_steps) {
-            r = build_items(c, c->host_active);  // counts only shrink: fewer items
+            r = rebuild();  // counts only shrink: fewer items
             if (r != GCCD_OK) return r;
         }
     }
@@ -694,6 +1025,7 @@ int gccd_run(gccd_ctx* c, double dt_ps, int64_t max_steps, int64_t* steps_done,
     const int64_t last = (k > 0) ? (int64_t)(uint32_t)c->host_meta[kMetaLast] : step0;
     c->step = (last > step0) ? last : step0;
     c->n_active = bound;
+    if (use_closure) c->closure_steps += c->step - step0;
     if (steps_done) *steps_done = c->step - step0;
     if (n_active) *n_active = c->n_active;
     return GCCD_OK;
@@ -712,14 +1044,25 @@ int gccd_field(gccd_ctx* c, double* ex, double* ey, double* ez) {
         int r = finish_list(c);
         if (r != GCCD_OK) return r;
     }
-    std::vector<uint32_t> all(c->n_events);
-    for (uint32_t e = 0; e < c->n_events; ++e) all[e] = c->off_h[e + 1] - c->off_h[e];
-    int r = build_items(c, all.data());
-    if (r != GCCD_OK) return r;
-    FieldArgs fa = field_args(c, true);
-    GCCD_HIP(c, launch_field(fa, c->tpt, c->precision, c->n_items, c->stream));
-    GCCD_HIP(c, launch_field_finish(c->part, n, c->ev_chunks_d, c->keys[c->cur], c->ev_off_d,
-                                    c->kl, n, c->K, ex, ey, ez, c->stream));
+    if (closure_applies(c)) {
+        choose_near_chunks(c);
+        int r = ensure_closure_capacity(c);
+        if (r == GCCD_OK) r = set_groups(c, 1);
+        if (r == GCCD_OK) r = build_near_items(c, n);
+        if (r == GCCD_OK) r = closure_field(c, true, n, true);
+        if (r != GCCD_OK) return r;
+    } else {
+        int r = set_groups(c, 0);
+        if (r != GCCD_OK) return r;
+        std::vector<uint32_t> all(c->n_events);
+        for (uint32_t e = 0; e < c->n_events; ++e) all[e] = c->off_h[e + 1] - c->off_h[e];
+        r = build_items(c, all.data());
+        if (r != GCCD_OK) return r;
+        FieldArgs fa = field_args(c, true);
+        GCCD_HIP(c, launch_field(fa, c->tpt, c->precision, c->n_items, c->stream));
+    }
+    GCCD_HIP(c, launch_field_finish(c->part, n, c->ev_chunks_d, 0, 0, c->keys[c->cur],
+                                    c->ev_off_d, c->kl, n, c->K, ex, ey, ez, c->stream));
     GCCD_HIP(c, hipStreamSynchronize(c->stream));  // host_items may be rebuilt next
     return GCCD_OK;
 }
@@ -781,6 +1124,8 @@ int gccd_stats(gccd_ctx* c, gccd_stats_t* out) {
     out->pair_interactions = meta64(c, kMetaStats + 2);
     out->n_events = c->n_events;
     out->max_source_chunks = c->max_chunks;
+    out->closure_steps = c->closure_steps;
+    out->near_chunks = c->near_chunks;
     return GCCD_OK;
 }
 

@@ -111,14 +111,72 @@ hipError_t launch_count(const uint64_t* keys, const uint32_t* ev_off, uint32_t n
                         KeyLayout kl, int sources_all, uint32_t* ev_active,
                         unsigned long long* pending, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
+// Sums the partial groups [g0, g0 + ev_chunks[e]) (or [g0, g0 + groups) when
+// groups > 0) of every slot and writes K times the sum in carrier order.
 hipError_t launch_field_finish(const float* part, uint32_t pstride, const int32_t* ev_chunks,
-                               const uint64_t* keys, const uint32_t* ev_off, KeyLayout kl,
-                               uint32_t n, double K, double* ex, double* ey, double* ez,
-                               hipStream_t s);
+                               int g0, int groups, const uint64_t* keys, const uint32_t* ev_off,
+                               KeyLayout kl, uint32_t n, double K, double* ex, double* ey,
+                               double* ez, hipStream_t s);
 hipError_t launch_image(const double* x, const double* y, const int32_t* cstep,
                         const uint32_t* ev_of, uint32_t n, int per_event, double x0, double y0,
                         double pitch, int32_t nx, int32_t ny, uint32_t* counts,
                         unsigned long long* n_out, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Far-field closure: the Eq. (6) sum split at a distance a into an exact
+// near part (near_tiles) and a far part read from a 32^3 grid through a
+// linear U-Net (bf16 MFMA convolutions) and Catmull-Rom interpolation.
+// ---------------------------------------------------------------------------
+constexpr int kGrid = 32;                    // nodes per axis
+constexpr int kGridNodes = kGrid * kGrid * kGrid;
+constexpr double kSigmaCells = 0.5;          // h = 0.5 x rms width per axis
+constexpr double kMaxDevCells = 14.0;        // no charge farther than 14 h from the centroid
+constexpr double kNearCells = 0.8;           // a = 0.8 h
+constexpr int kMomBlocks = 512;              // fixed partition of the placement reduction
+
+// Written on the device each time the closure field is computed.
+struct GridParams {
+    double origin[3];   // node 0 on each axis, um (node k at origin + k h)
+    double h;           // node spacing, um
+    double inv_h;
+    double a2;          // a^2, um^2: source tiles farther than a are skipped
+    double cut2;        // a^2 + eps^2: a pair counts while r^2 + eps^2 < cut2
+    double inv_h2;      // 1 / h^2: the network's field unit K / h^2, over K
+};
+
+// One convolution of the network: out = W * in over a cubic grid of n^3
+// nodes, channels last.  The input is channels [in_off, in_off + cin) of
+// rows of in_stride bf16; the output goes to channels [out_off, out_off +
+// cout) of rows of out_stride bf16, or to rows of 4 floats (the field).
+struct ConvArgs {
+    const uint16_t* in;
+    int32_t in_stride, in_off, cin;
+    const uint16_t* wpk;    // weights packed per 32-deep K slice and 16-wide N tile
+    int32_t nslice, ntile, taps, n;
+    uint16_t* out;          // bf16 output, or NULL
+    float* outf;            // FP32 output [n^3][4], or NULL
+    int32_t out_stride, out_off, cout;
+};
+
+hipError_t launch_near(const FieldArgs& a, const GridParams* gp, uint32_t n_items,
+                       hipStream_t s);
+hipError_t launch_moments(const double* x, const double* y, const double* z, uint32_t n,
+                          double* part, hipStream_t s);
+hipError_t launch_grid_params(const double* part, const double* x, const double* y,
+                              const double* z, uint32_t n, double eps2, GridParams* gp,
+                              hipStream_t s);
+hipError_t launch_deposit(const double* px, const double* py, const double* pz, uint32_t n,
+                          const GridParams* gp, unsigned long long* acc, hipStream_t s);
+hipError_t launch_rho(const unsigned long long* acc, uint16_t* rho_bf16, float* rho_f32,
+                      hipStream_t s);
+hipError_t launch_conv(const ConvArgs& a, hipStream_t s);
+hipError_t launch_pool(const uint16_t* in, int in_stride, int in_off, int c, int n_fine,
+                       uint16_t* out, hipStream_t s);
+hipError_t launch_upsample(const uint16_t* in, int c, int m, uint16_t* out, int out_stride,
+                           int out_off, hipStream_t s);
+hipError_t launch_far(const float* F, const GridParams* gp, const double* px, const double* py,
+                      const double* pz, uint32_t nt, float* ox, float* oy, float* oz,
+                      hipStream_t s);
 
 // Sorting of key lists (rocPRIM radix sort; storage provided by the caller).
 hipError_t sort_keys_storage(uint32_t n, uint32_t end_bit, size_t* bytes);

@@ -134,7 +134,9 @@ enum : int {
     kDiffAll = 2    // hi and lo parts for every pair (double-single differences)
 };
 
-template <int TPT, int DIFF>
+// CUT: the term counts only when r^2 + eps^2 < cut2 (the near part of a
+// near/far split); 2 more VALU per pair.
+template <int TPT, int DIFF, bool CUT = false>
 __device__ __forceinline__ void pair_terms(const float* __restrict__ lxp,
                                            const float* __restrict__ lyp,
                                            const float* __restrict__ lzp, uint32_t k, float shx,
@@ -143,7 +145,8 @@ __device__ __forceinline__ void pair_terms(const float* __restrict__ lxp,
                                            const float (&thz)[TPT], const float (&tlx)[TPT],
                                            const float (&tly)[TPT], const float (&tlz)[TPT],
                                            float eps2, float rc2, float (&ax)[TPT],
-                                           float (&ay)[TPT], float (&az)[TPT]) {
+                                           float (&ay)[TPT], float (&az)[TPT],
+                                           float cut2 = 0.0f) {
     float dx[TPT], dy[TPT], dz[TPT], r2[TPT];
     bool near = false;
 #pragma unroll
@@ -182,7 +185,8 @@ __device__ __forceinline__ void pair_terms(const float* __restrict__ lxp,
         // r^-3 as rsq^3: one transcendental and two multiplies measured
         // faster on gfx950 than rsq * rcp (two transcendentals, one multiply)
         const float inv = __builtin_amdgcn_rsqf(r2[t]);
-        const float w = inv * inv * inv;
+        float w = inv * inv * inv;
+        if (CUT) w = r2[t] < cut2 ? w : 0.0f;
         ax[t] = __builtin_fmaf(dx[t], w, ax[t]);
         ay[t] = __builtin_fmaf(dy[t], w, ay[t]);
         az[t] = __builtin_fmaf(dz[t], w, az[t]);
@@ -190,7 +194,7 @@ __device__ __forceinline__ void pair_terms(const float* __restrict__ lxp,
 }
 
 // All pairs of one staged tile (cnt sources) with the lane's TPT targets.
-template <int TPT, int DIFF>
+template <int TPT, int DIFF, bool CUT = false>
 __device__ __forceinline__ void tile_terms(const float* __restrict__ hxp,
                                            const float* __restrict__ hyp,
                                            const float* __restrict__ hzp,
@@ -201,7 +205,8 @@ __device__ __forceinline__ void tile_terms(const float* __restrict__ hxp,
                                            const float (&thz)[TPT], const float (&tlx)[TPT],
                                            const float (&tly)[TPT], const float (&tlz)[TPT],
                                            float eps2, float rc2, float (&bx)[TPT],
-                                           float (&by)[TPT], float (&bz)[TPT]) {
+                                           float (&by)[TPT], float (&bz)[TPT],
+                                           float cut2 = 0.0f) {
     uint32_t k = 0;
     for (; k + 4 <= cnt; k += 4) {
         const float4 hx4 = *reinterpret_cast<const float4*>(hxp + k);
@@ -213,18 +218,22 @@ __device__ __forceinline__ void tile_terms(const float* __restrict__ hxp,
             ly4 = *reinterpret_cast<const float4*>(lyp + k);
             lz4 = *reinterpret_cast<const float4*>(lzp + k);
         }
-        pair_terms<TPT, DIFF>(lxp, lyp, lzp, k + 0, hx4.x, hy4.x, hz4.x, lx4.x, ly4.x, lz4.x, thx,
-                              thy, thz, tlx, tly, tlz, eps2, rc2, bx, by, bz);
-        pair_terms<TPT, DIFF>(lxp, lyp, lzp, k + 1, hx4.y, hy4.y, hz4.y, lx4.y, ly4.y, lz4.y, thx,
-                              thy, thz, tlx, tly, tlz, eps2, rc2, bx, by, bz);
-        pair_terms<TPT, DIFF>(lxp, lyp, lzp, k + 2, hx4.z, hy4.z, hz4.z, lx4.z, ly4.z, lz4.z, thx,
-                              thy, thz, tlx, tly, tlz, eps2, rc2, bx, by, bz);
-        pair_terms<TPT, DIFF>(lxp, lyp, lzp, k + 3, hx4.w, hy4.w, hz4.w, lx4.w, ly4.w, lz4.w, thx,
-                              thy, thz, tlx, tly, tlz, eps2, rc2, bx, by, bz);
+        pair_terms<TPT, DIFF, CUT>(lxp, lyp, lzp, k + 0, hx4.x, hy4.x, hz4.x, lx4.x, ly4.x, lz4.x, thx,
+                              thy, thz, tlx, tly, tlz, eps2, rc2, bx, by, bz,
+                                   cut2);
+        pair_terms<TPT, DIFF, CUT>(lxp, lyp, lzp, k + 1, hx4.y, hy4.y, hz4.y, lx4.y, ly4.y, lz4.y, thx,
+                              thy, thz, tlx, tly, tlz, eps2, rc2, bx, by, bz,
+                                   cut2);
+        pair_terms<TPT, DIFF, CUT>(lxp, lyp, lzp, k + 2, hx4.z, hy4.z, hz4.z, lx4.z, ly4.z, lz4.z, thx,
+                              thy, thz, tlx, tly, tlz, eps2, rc2, bx, by, bz,
+                                   cut2);
+        pair_terms<TPT, DIFF, CUT>(lxp, lyp, lzp, k + 3, hx4.w, hy4.w, hz4.w, lx4.w, ly4.w, lz4.w, thx,
+                              thy, thz, tlx, tly, tlz, eps2, rc2, bx, by, bz,
+                                   cut2);
     }
     for (; k < cnt; ++k) {
-        pair_terms<TPT, DIFF>(lxp, lyp, lzp, k, hxp[k], hyp[k], hzp[k], lxp[k], lyp[k], lzp[k], thx,
-                              thy, thz, tlx, tly, tlz, eps2, rc2, bx, by, bz);
+        pair_terms<TPT, DIFF, CUT>(lxp, lyp, lzp, k, hxp[k], hyp[k], hzp[k], lxp[k], lyp[k], lzp[k],
+                                   thx, thy, thz, tlx, tly, tlz, eps2, rc2, bx, by, bz, cut2);
     }
 }
 
@@ -550,6 +559,222 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles_f64(FieldArgs a) {
             a.part[(size_t)((step_t + chunk) * 3 + d) * a.pstride + off + ts] = lo;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Near part of the closure's split of Eq. (6): the same sum over the
+// sources closer than a only (r^2 + eps^2 < a^2 + eps^2).  Work items,
+// origins, hi/lo staging and the close-pair recomputation are those of
+// field_tiles; the difference is which tiles are visited.  The item's
+// candidate tiles (chunk, chunk + S, ...) are tested 256 at a time against
+// the targets' box, the ones within a are compacted into an LDS list, and
+// only those are staged and summed.  A tile entirely within a of every
+// target skips the per-pair cutoff.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kFieldThreads) void near_tiles(FieldArgs a, const GridParams* gp) {
+    __shared__ __align__(16) float sh[2][6][kTile];
+    __shared__ double box[6][kFieldThreads / 64];
+    __shared__ double tbox[2][6];
+    __shared__ uint32_t list[kFieldThreads];
+    __shared__ uint32_t wcount[kFieldThreads / 64];
+
+    const FieldItem it = a.items[blockIdx.x];
+    const uint32_t off = a.ev_off[it.event];
+    const uint32_t ne = a.ev_off[it.event + 1] - off;
+    const uint32_t na = a.ev_active[it.event];
+    const uint32_t nt = a.targets_all ? ne : na;
+    const uint32_t ns = a.sources_all ? ne : na;
+    const uint32_t tbase = it.blk * (uint32_t)kFieldThreads;
+    if (tbase >= nt) return;
+    const uint32_t ntiles = (ns + kTile - 1) / kTile;
+    const uint32_t tile0 = a.ev_tile[it.event];
+    const uint32_t chunk = it.chunk;
+    const uint32_t step_t = it.nchunk;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+
+    const uint32_t ts = tbase + (uint32_t)tid;
+    double px = 0.0, py = 0.0, pz = 0.0;
+    double lo_x = INFINITY, lo_y = INFINITY, lo_z = INFINITY;
+    double hi_x = -INFINITY, hi_y = -INFINITY, hi_z = -INFINITY;
+    if (ts < nt) {
+        px = a.px[off + ts];
+        py = a.py[off + ts];
+        pz = a.pz[off + ts];
+        lo_x = hi_x = px;
+        lo_y = hi_y = py;
+        lo_z = hi_z = pz;
+    }
+    lo_x = wave_min(lo_x);
+    lo_y = wave_min(lo_y);
+    lo_z = wave_min(lo_z);
+    hi_x = wave_max(hi_x);
+    hi_y = wave_max(hi_y);
+    hi_z = wave_max(hi_z);
+    if (lane == 0) {
+        box[0][wave] = lo_x;
+        box[1][wave] = lo_y;
+        box[2][wave] = lo_z;
+        box[3][wave] = hi_x;
+        box[4][wave] = hi_y;
+        box[5][wave] = hi_z;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < kFieldThreads / 64; ++w) {
+        lo_x = fmin(lo_x, box[0][w]);
+        lo_y = fmin(lo_y, box[1][w]);
+        lo_z = fmin(lo_z, box[2][w]);
+        hi_x = fmax(hi_x, box[3][w]);
+        hi_y = fmax(hi_y, box[4][w]);
+        hi_z = fmax(hi_z, box[5][w]);
+    }
+    lo_x = uniform(lo_x);
+    lo_y = uniform(lo_y);
+    lo_z = uniform(lo_z);
+    hi_x = uniform(hi_x);
+    hi_y = uniform(hi_y);
+    hi_z = uniform(hi_z);
+    const double ox = 0.5 * (lo_x + hi_x), oy = 0.5 * (lo_y + hi_y), oz = 0.5 * (lo_z + hi_z);
+    const double hx = 0.5 * (hi_x - lo_x), hy = 0.5 * (hi_y - lo_y), hz = 0.5 * (hi_z - lo_z);
+    const double rc2d = 0.0625 * (hx * hx + hy * hy + hz * hz);
+    const float rc2 = uniform((float)rc2d);
+    const double a2 = uniform(gp->a2);
+    const float cut2 = uniform((float)gp->cut2);
+
+    float thx[1], thy[1], thz[1], tlx[1], tly[1], tlz[1], ax[1], ay[1], az[1];
+    {
+        const double rx = px - ox, ry = py - oy, rz = pz - oz;
+        thx[0] = (float)rx;
+        thy[0] = (float)ry;
+        thz[0] = (float)rz;
+        tlx[0] = (float)(rx - (double)thx[0]);
+        tly[0] = (float)(ry - (double)thy[0]);
+        tlz[0] = (float)(rz - (double)thz[0]);
+        ax[0] = ay[0] = az[0] = 0.0f;
+    }
+
+    double qx = 0.0, qy = 0.0, qz = 0.0, qb = 0.0;
+    auto fetch = [&](uint32_t t) {
+        const uint32_t i = t * kTile + (uint32_t)tid;
+        qx = ox;
+        qy = oy;
+        qz = oz;
+        if (i < ns) {
+            qx = a.px[off + i];
+            qy = a.py[off + i];
+            qz = a.pz[off + i];
+        }
+        if (tid < 6) qb = a.tile_box[(size_t)tid * a.tile_stride + tile0 + t];
+    };
+    auto stage = [&](int b) {
+        if (tid < 6) tbox[b][tid] = qb;
+        const double rx = qx - ox, ry = qy - oy, rz = qz - oz;
+        const float fx = (float)rx, fy = (float)ry, fz = (float)rz;
+        sh[b][0][tid] = fx;
+        sh[b][1][tid] = fy;
+        sh[b][2][tid] = fz;
+        sh[b][3][tid] = (float)(rx - (double)fx);
+        sh[b][4][tid] = (float)(ry - (double)fy);
+        sh[b][5][tid] = (float)(rz - (double)fz);
+    };
+
+    const uint32_t ncand = chunk < ntiles ? (ntiles - chunk + step_t - 1) / step_t : 0u;
+    for (uint32_t base = 0; base < ncand; base += kFieldThreads) {
+        // 1. which of the next 256 candidate tiles come within a of the targets
+        const uint32_t m = base + (uint32_t)tid;
+        bool keep = false;
+        uint32_t t = 0;
+        if (m < ncand) {
+            t = chunk + m * step_t;
+            const size_t g = (size_t)tile0 + t;
+            const double* tb = a.tile_box;
+            const size_t st = a.tile_stride;
+            const double gx = fmax(0.0, fmax(tb[0 * st + g] - hi_x, lo_x - tb[3 * st + g]));
+            const double gy = fmax(0.0, fmax(tb[1 * st + g] - hi_y, lo_y - tb[4 * st + g]));
+            const double gz = fmax(0.0, fmax(tb[2 * st + g] - hi_z, lo_z - tb[5 * st + g]));
+            keep = gx * gx + gy * gy + gz * gz < a2;
+        }
+        // 2. compact them, in candidate order, into the LDS list
+        const uint64_t bal = __ballot(keep);
+        if (lane == 0) wcount[wave] = (uint32_t)__popcll(bal);
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < kFieldThreads / 64; ++w) {
+            const uint32_t cw = wcount[w];
+            if (w < wave) before += cw;
+            total += cw;
+        }
+        if (keep) list[before + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull))] = t;
+        __syncthreads();
+        // 3. the kept tiles, double buffered as in field_tiles
+        int buf = 0;
+        if (total > 0) {
+            fetch(list[0]);
+            stage(0);
+        }
+        __syncthreads();
+        for (uint32_t q = 0; q < total; ++q) {
+            const uint32_t tt = list[q];
+            const bool more = q + 1 < total;
+            if (more) fetch(list[q + 1]);
+            const uint32_t cnt = min((uint32_t)kTile, ns - tt * kTile);
+            float bx[1] = {0.0f}, by[1] = {0.0f}, bz[1] = {0.0f};
+            const float* hxp = sh[buf][0];
+            const float* hyp = sh[buf][1];
+            const float* hzp = sh[buf][2];
+            const float* lxp = sh[buf][3];
+            const float* lyp = sh[buf][4];
+            const float* lzp = sh[buf][5];
+            const double* tb = tbox[buf];
+            const double gx = fmax(0.0, fmax(tb[0] - hi_x, lo_x - tb[3]));
+            const double gy = fmax(0.0, fmax(tb[1] - hi_y, lo_y - tb[4]));
+            const double gz = fmax(0.0, fmax(tb[2] - hi_z, lo_z - tb[5]));
+            const bool far_tile = gx * gx + gy * gy + gz * gz >= rc2d;
+            // largest distance between the two boxes: every pair well inside a
+            // (a margin far above the FP32 error of r^2) needs no per-pair test
+            const double mx = fmax(tb[3] - lo_x, hi_x - tb[0]);
+            const double my = fmax(tb[4] - lo_y, hi_y - tb[1]);
+            const double mz = fmax(tb[5] - lo_z, hi_z - tb[2]);
+            const bool inside = mx * mx + my * my + mz * mz < 0.9999 * a2;
+            if (inside) {
+                if (far_tile)
+                    tile_terms<1, kDiffHi, false>(hxp, hyp, hzp, lxp, lyp, lzp, cnt, thx, thy, thz,
+                                                  tlx, tly, tlz, a.eps2, rc2, bx, by, bz);
+                else
+                    tile_terms<1, kDiffNear, false>(hxp, hyp, hzp, lxp, lyp, lzp, cnt, thx, thy,
+                                                    thz, tlx, tly, tlz, a.eps2, rc2, bx, by, bz);
+            } else {
+                if (far_tile)
+                    tile_terms<1, kDiffHi, true>(hxp, hyp, hzp, lxp, lyp, lzp, cnt, thx, thy, thz,
+                                                 tlx, tly, tlz, a.eps2, rc2, bx, by, bz, cut2);
+                else
+                    tile_terms<1, kDiffNear, true>(hxp, hyp, hzp, lxp, lyp, lzp, cnt, thx, thy,
+                                                   thz, tlx, tly, tlz, a.eps2, rc2, bx, by, bz,
+                                                   cut2);
+            }
+            ax[0] += bx[0];
+            ay[0] += by[0];
+            az[0] += bz[0];
+            if (more) stage(buf ^ 1);
+            __syncthreads();
+            buf ^= 1;
+        }
+    }
+
+    if (ts < nt) {
+        a.part[(size_t)(chunk * 3 + 0) * a.pstride + off + ts] = ax[0];
+        a.part[(size_t)(chunk * 3 + 1) * a.pstride + off + ts] = ay[0];
+        a.part[(size_t)(chunk * 3 + 2) * a.pstride + off + ts] = az[0];
+    }
+}
+
+hipError_t launch_near(const FieldArgs& a, const GridParams* gp, uint32_t n_items,
+                       hipStream_t s) {
+    if (n_items == 0) return hipSuccess;
+    near_tiles<<<n_items, kFieldThreads, 0, s>>>(a, gp);
+    return hipGetLastError();
 }
 
 template <int PREC>
@@ -915,8 +1140,9 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
 // FP64 in chunk order, times K (same reduction as step_update), written back
 // to the carrier each slot holds.
 __global__ void field_finish(const float* part, uint32_t pstride, const int32_t* ev_chunks,
-                             const uint64_t* keys, const uint32_t* ev_off, KeyLayout kl,
-                             uint32_t n, double K, double* ex, double* ey, double* ez) {
+                             int g0, int groups, const uint64_t* keys, const uint32_t* ev_off,
+                             KeyLayout kl, uint32_t n, double K, double* ex, double* ey,
+                             double* ez) {
     for (uint32_t slot = blockIdx.x * blockDim.x + threadIdx.x; slot < n;
          slot += gridDim.x * blockDim.x) {
         const uint64_t key = keys[slot];
@@ -924,8 +1150,8 @@ __global__ void field_finish(const float* part, uint32_t pstride, const int32_t*
         const uint32_t off = ev_off[e], ne = ev_off[e + 1] - off;
         const uint32_t j = off + min(key_local(key, kl), ne - 1u);
         double sx = 0.0, sy = 0.0, sz = 0.0;
-        const int nchunk = ev_chunks[e];
-        for (int c = 0; c < nchunk; ++c) {
+        const int g1 = g0 + (groups > 0 ? groups : ev_chunks[e]);
+        for (int c = g0; c < g1; ++c) {
             sx += (double)part[(size_t)(c * 3 + 0) * pstride + slot];
             sy += (double)part[(size_t)(c * 3 + 1) * pstride + slot];
             sz += (double)part[(size_t)(c * 3 + 2) * pstride + slot];
@@ -937,11 +1163,11 @@ __global__ void field_finish(const float* part, uint32_t pstride, const int32_t*
 }
 
 hipError_t launch_field_finish(const float* part, uint32_t pstride, const int32_t* ev_chunks,
-                               const uint64_t* keys, const uint32_t* ev_off, KeyLayout kl,
-                               uint32_t n, double K, double* ex, double* ey, double* ez,
-                               hipStream_t s) {
-    field_finish<<<grid_for(n, 256, 8192), 256, 0, s>>>(part, pstride, ev_chunks, keys, ev_off,
-                                                         kl, n, K, ex, ey, ez);
+                               int g0, int groups, const uint64_t* keys, const uint32_t* ev_off,
+                               KeyLayout kl, uint32_t n, double K, double* ex, double* ey,
+                               double* ez, hipStream_t s) {
+    field_finish<<<grid_for(n, 256, 8192), 256, 0, s>>>(part, pstride, ev_chunks, g0, groups, keys,
+                                                         ev_off, kl, n, K, ex, ey, ez);
     return hipGetLastError();
 }
 

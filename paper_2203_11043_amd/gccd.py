@@ -14,7 +14,8 @@ import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgccd.so")
-ABI_VERSION = 1
+ABI_VERSION = 2
+CLOSURE_WEIGHTS = 290784      # GCCD_CLOSURE_WEIGHTS
 
 GCCD_OK = 0
 GCCD_E_INVALID = -1
@@ -36,8 +37,8 @@ PRECISION_MODES = {"default": 0, "block": 1, "event": 2, "absolute": 3, "compens
 # every symbol the header declares
 EXPORTS = ("gccd_init", "gccd_load", "gccd_load_events", "gccd_run", "gccd_image",
            "gccd_image_events", "gccd_field", "gccd_positions", "gccd_stats",
-           "gccd_set_launch", "gccd_set_precision", "gccd_set_timing", "gccd_strerror",
-           "gccd_last_error", "gccd_destroy")
+           "gccd_set_launch", "gccd_set_precision", "gccd_set_closure", "gccd_closure_parts",
+           "gccd_set_timing", "gccd_strerror", "gccd_last_error", "gccd_destroy")
 
 
 class CParams(ctypes.Structure):
@@ -74,6 +75,8 @@ class CStats(ctypes.Structure):
         ("source_chunks", ctypes.c_int32),
         ("n_events", ctypes.c_int64),
         ("max_source_chunks", ctypes.c_int64),
+        ("closure_steps", ctypes.c_int64),
+        ("near_chunks", ctypes.c_int64),
     ]
 
 
@@ -94,6 +97,8 @@ def _load():
     L.gccd_stats.argtypes = [P, ctypes.POINTER(CStats)]
     L.gccd_set_launch.argtypes = [P, i32, i32]
     L.gccd_set_precision.argtypes = [P, i32]
+    L.gccd_set_closure.argtypes = [P, P, i64, i64]
+    L.gccd_closure_parts.argtypes = [P, P, P, P, P, P, P, P, P]
     L.gccd_set_timing.argtypes = [P, i32]
     L.gccd_strerror.argtypes = [ctypes.c_int]
     L.gccd_strerror.restype = ctypes.c_char_p
@@ -233,6 +238,31 @@ def gccd_field(ctx: int, n: int, out=None):
                           device=torch.device("cuda", torch.cuda.current_device()))
     _check(ctx, lib.gccd_field(ctx, out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr()))
     return out
+
+
+def gccd_set_closure(ctx: int, weights, min_carriers: int = 0) -> None:
+    """weights: GCCD_CLOSURE_WEIGHTS floats (any array-like) or None to disable."""
+    if weights is None:
+        _check(ctx, lib.gccd_set_closure(ctx, None, 0, 0))
+        return
+    import numpy as np
+    w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32).ravel())
+    _check(ctx, lib.gccd_set_closure(ctx, w.ctypes.data_as(ctypes.c_void_p), int(w.size),
+                                     int(min_carriers)))
+
+
+def gccd_closure_parts(ctx: int, n: int):
+    """Returns (near (3, n) float64, far (3, n) float64, rho (32, 32, 32) float32,
+    grid (4,) float64: node-0 position and spacing) as device tensors."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    near = torch.empty((3, n), dtype=torch.float64, device=dev)
+    far = torch.empty((3, n), dtype=torch.float64, device=dev)
+    rho = torch.empty((32, 32, 32), dtype=torch.float32, device=dev)
+    grid = torch.empty(4, dtype=torch.float64, device=dev)
+    _check(ctx, lib.gccd_closure_parts(ctx, near[0].data_ptr(), near[1].data_ptr(),
+                                       near[2].data_ptr(), far[0].data_ptr(), far[1].data_ptr(),
+                                       far[2].data_ptr(), rho.data_ptr(), grid.data_ptr()))
+    return near, far, rho, grid
 
 
 def gccd_positions(ctx: int, n: int):

@@ -1,0 +1,190 @@
+"""The far-field closure on the GPU against its FP64 oracle (oracle/closure.py).
+
+Each part is compared on the same positions, with seeded random weights
+(the construction is linear, so any weights exercise every kernel):
+  * placement (grid origin and spacing): 1e-12 relative;
+  * deposit: FP32 rounding of fixed-point sums, 1e-6 relative + 1e-5;
+  * near sum: the Eq. (6) tolerance 1e-5 of A_near (sum of the term
+    magnitudes) plus the terms of pairs within 1e-5 relative of the cutoff
+    a, whose side of the cutoff FP32 rounding may decide either way;
+  * far field: the network in bf16 against the oracle's network rounded to
+    bf16 at the same points.  The two differ only where an FP32 and an FP64
+    sum round to different bf16 neighbours (one unit, 2^-8 relative); the
+    bound used is 2 % of the largest far-field value, observed far lower.
+Also: the closure's gccd_field is its two parts added; loads the closure
+does not apply to fall back to the exact path; runs are deterministic.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import closure as C  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def g():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_11043_amd import gccd
+    return gccd
+
+
+@pytest.fixture(scope="module")
+def W():
+    from paper_2203_11043_amd import workloads
+    return workloads
+
+
+def gpu(*arrs):
+    return [torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda() for a in arrs]
+
+
+def random_weights(seed):
+    """Zero-mean weights scaled by 1/sqrt(fan-in), so the linear network
+    neither grows nor vanishes."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _, shape in C.weight_shapes():
+        fan_in = int(np.prod(shape[1:]))
+        out.append(rng.normal(0.0, 1.0 / math.sqrt(fan_in), size=shape).ravel())
+    return np.concatenate(out)
+
+
+def parts(g, W, x, y, z, weights, **dev):
+    d = dict(W.DEVICE, **dev)
+    ctx = g.gccd_init(g.Params.from_device(d))
+    try:
+        if weights is not None:
+            g.gccd_set_closure(ctx, weights, 0)
+        g.gccd_load(ctx, *gpu(x, y, z))
+        near, far, rho, grid = g.gccd_closure_parts(ctx, len(x))
+        return (near.cpu().numpy(), far.cpu().numpy(), rho.cpu().numpy(),
+                grid.cpu().numpy(), g.gccd_stats(ctx))
+    finally:
+        g.gccd_destroy(ctx)
+
+
+@pytest.mark.parametrize("n,seed", [(3000, 1), (20000, 2)])
+def test_closure_parts_match_oracle(g, W, orc, n, seed):
+    w = W.single_cloud(n, seed=seed, depth_um=200.0)
+    wt = random_weights(seed)
+    near, far, rho, grid, st = parts(g, W, w.x, w.y, w.z, wt)
+    src = [w.x, w.y, w.z]
+
+    origin, h = C.placement(*src)
+    assert np.allclose(grid[:3], origin, rtol=0, atol=1e-12 * 1000) and \
+        abs(grid[3] / h - 1) < 1e-12, (grid, origin, h)
+
+    rho_o = C.deposit(*src, origin, h)
+    assert np.allclose(rho, rho_o, rtol=1e-6, atol=1e-5), np.max(np.abs(rho - rho_o))
+    assert abs(rho.sum() - n) < 1e-3
+
+    # near part at sampled targets
+    a = C.NEAR_CELLS * h
+    idx = np.random.default_rng(seed).choice(n, 300, replace=False)
+    t = [v[idx] for v in src]
+    Eo = orc.field_window(t, src, 0.0, a)
+    shell = orc.field_window(t, src, a * (1 - 1e-5), a * (1 + 1e-5))
+    _, Aall = orc.field(t, src, with_magnitude=True)
+    dn = np.linalg.norm(near[:, idx] - Eo, axis=0)
+    allow = 1e-5 * Aall + np.linalg.norm(shell, axis=0) + 1e-9
+    print(f"[closure] n={n} near: max |dE|/allowance = {np.max(dn / allow):.3f}", flush=True)
+    assert np.all(dn <= allow)
+
+    # far part: the oracle's network with bf16 rounding at the GPU's points
+    F = C.network(rho_o, wt, quantize=C.bf16)
+    Kc = orc.coulomb_constant(11.7)
+    far_o = Kc / (h * h) * C.interpolate(F, *t, origin, h)
+    df = np.abs(far[:, idx] - far_o)
+    scale = np.max(np.abs(far_o))
+    print(f"[closure] n={n} far: max |dF| / max |F| = {df.max() / scale:.2e}, "
+          f"rms ratio {np.sqrt(np.mean(df**2)) / np.sqrt(np.mean(far_o**2)):.2e}", flush=True)
+    assert df.max() <= 2e-2 * scale
+
+
+def test_closure_field_is_its_parts(g, W):
+    w = W.single_cloud(30000, seed=3, depth_um=300.0)
+    wt = random_weights(3)
+    near, far, _, _, _ = parts(g, W, w.x, w.y, w.z, wt)
+    d = dict(W.DEVICE)
+    ctx = g.gccd_init(g.Params.from_device(d))
+    try:
+        g.gccd_set_closure(ctx, wt, 0)
+        g.gccd_load(ctx, *gpu(w.x, w.y, w.z))
+        E = g.gccd_field(ctx, w.n).cpu().numpy()
+    finally:
+        g.gccd_destroy(ctx)
+    s = near + far
+    assert np.allclose(E, s, rtol=1e-12, atol=1e-12 * np.abs(s).max())
+
+
+def test_closure_without_weights_gives_near_part_only(g, W, orc):
+    w = W.single_cloud(5000, seed=4, depth_um=100.0)
+    near, far, rho, grid, _ = parts(g, W, w.x, w.y, w.z, None)
+    assert np.all(far == 0.0) and np.all(np.isfinite(near))
+    assert abs(rho.sum() - 5000) < 1e-3
+
+
+def test_closure_fallbacks(g, W):
+    """Loads the closure does not apply to run the exact path unchanged:
+    fewer holes than min_carriers, several events, no repulsion."""
+    w = W.single_cloud(4000, seed=5, depth_um=40.0)
+    d = dict(W.DEVICE, event=3)
+    wt = random_weights(5)
+
+    def run(closure_min, events=False, **kw):
+        dd = dict(d, **kw)
+        ctx = g.gccd_init(g.Params.from_device(dd))
+        try:
+            if closure_min is not None:
+                g.gccd_set_closure(ctx, wt, closure_min)
+            if events:
+                g.gccd_load_events(ctx, [0, 2000, 4000], *gpu(w.x, w.y, w.z))
+            else:
+                g.gccd_load(ctx, *gpu(w.x, w.y, w.z))
+            g.gccd_run(ctx, 10.0, 40)
+            pos, cs = g.gccd_positions(ctx, w.n)
+            return pos.cpu().numpy(), g.gccd_stats(ctx)
+        finally:
+            g.gccd_destroy(ctx)
+
+    exact, _ = run(None)
+    small, st = run(4001)
+    assert st["closure_steps"] == 0 and np.array_equal(small, exact)
+    used, st = run(0)
+    assert st["closure_steps"] == 40 and not np.array_equal(used, exact)
+    ev_exact, _ = run(None, events=True)
+    ev, st = run(0, events=True)
+    assert st["closure_steps"] == 0 and np.array_equal(ev, ev_exact)
+    off_exact, _ = run(None, coulomb=0)
+    off, st = run(0, coulomb=0)
+    assert st["closure_steps"] == 0 and np.array_equal(off, off_exact)
+
+
+def test_closure_run_is_deterministic_and_resumable(g, W):
+    w = W.single_cloud(20000, seed=6, depth_um=60.0)
+    wt = random_weights(6) * 0.1
+    d = dict(W.DEVICE, event=1)
+
+    def run(chunks):
+        ctx = g.gccd_init(g.Params.from_device(d))
+        try:
+            g.gccd_set_closure(ctx, wt, 0)
+            g.gccd_load(ctx, *gpu(w.x, w.y, w.z))
+            for k in chunks:
+                g.gccd_run(ctx, 10.0, k)
+            pos, cs = g.gccd_positions(ctx, w.n)
+            return pos.cpu().numpy(), cs.cpu().numpy()
+        finally:
+            g.gccd_destroy(ctx)
+
+    a = run([50])
+    b = run([17, 33])
+    c = run([50])
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert np.array_equal(a[0], c[0])
