@@ -93,20 +93,83 @@ def cpu_baseline(w, max_seconds: float = 12.0) -> dict:
                       f"FP64, {dt:.1f} s wall"}
 
 
+def closure_leg(gccd, workloads, torch, n: int = 1000000, seed: int = 2000,
+                closure_steps: int = 10, exact_steps: int = 3) -> dict:
+    """The closure against the exact path on one large cloud (width
+    0.5 um (n/1000)^(1/3), 300 um deep): time per step of each, measured the
+    same way (one time step per gccd_run, warm-up first), from the same
+    positions.  The accuracy figures come from the committed evaluation of
+    whole runs (closure_eval.py), not from this short run."""
+    import numpy as np
+    from paper_2203_11043_amd import closure_eval
+    if not os.path.exists(closure_eval.WEIGHTS):
+        return None
+    weights = closure_eval.load_weights()
+    x, y, z = workloads.gaussian_cloud(n, workloads.cloud_sigma(n), (480.0, 480.0, 300.0), seed,
+                                       stream=2)
+    xs = [torch.as_tensor(v).cuda() for v in (x, y, z)]
+    res = {}
+    for name, use, warm, steps in (("closure", True, 5, closure_steps),
+                                   ("exact", False, 2, exact_steps)):
+        ctx = gccd.gccd_init(gccd.Params.from_device(dict(workloads.DEVICE, event=seed)))
+        try:
+            if use:
+                gccd.gccd_set_closure(ctx, weights, 0)
+            gccd.gccd_load(ctx, *xs)
+            for _ in range(warm):
+                gccd.gccd_run(ctx, workloads.DT_PS, 1)
+            torch.cuda.synchronize()
+            s0 = gccd.gccd_stats(ctx)
+            gccd.gccd_set_timing(ctx, True)
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                gccd.gccd_run(ctx, workloads.DT_PS, 1)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            s1 = gccd.gccd_stats(ctx)
+        finally:
+            gccd.gccd_destroy(ctx)
+        cs = s1["carrier_steps"] - s0["carrier_steps"]
+        pairs = s1["pair_interactions"] - s0["pair_interactions"]
+        res[name] = {"ms_per_step": dt / steps * 1e3,
+                     "field_ms_per_step": (s1["field_ms"] - s0["field_ms"]) / steps,
+                     "carrier_steps_per_s": cs / dt,
+                     "pair_interactions_per_s_equivalent": pairs / dt,
+                     "closure_steps": s1["closure_steps"] - s0["closure_steps"],
+                     "steps": steps, "warmup": warm}
+    out = {"workload": f"single Gaussian cloud, n={n}, sigma={workloads.cloud_sigma(n):.2f} um, "
+                       f"depth 300 um, seed {seed}",
+           "closure": res["closure"], "exact": res["exact"],
+           "speedup": res["exact"]["ms_per_step"] / res["closure"]["ms_per_step"]}
+    ev = os.path.join(os.path.dirname(closure_eval.WEIGHTS), "closure_eval.json")
+    if os.path.exists(ev):
+        with open(ev) as f:
+            rec = json.load(f)["results"]
+        out["whole_run_accuracy"] = {
+            "source": os.path.relpath(ev, ROOT),
+            "var_x_rel": [r["var_x_rel"] for r in rec], "var_y_rel": [r["var_y_rel"] for r in rec],
+            "image_l1_over_n": [r["image_l1_over_n"] for r in rec],
+            "speedup_whole_run": [r["speedup"] for r in rec]}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", choices=("cloud", "batch"), default="cloud",
+    ap.add_argument("--workload", choices=("cloud", "batch", "closure"), default="cloud",
                     help="cloud: one 1e5-hole cloud (default); batch: 4096 clouds of "
-                         "200-20000 holes in one launch")
+                         "200-20000 holes in one launch; closure: only the closure-versus-"
+                         "exact leg on the 1e6-hole cloud (--steps closure steps)")
     ap.add_argument("--n", type=int, default=100000)
     ap.add_argument("--events", type=int, default=4096)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--tpt", type=int, default=0, help="targets per thread (0 = auto)")
     ap.add_argument("--chunks", type=int, default=0, help="source chunks (0 = auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-closure", action="store_true",
+                    help="skip the closure-versus-exact leg on the 1e6-hole cloud")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (counter scale)")
     args = ap.parse_args()
@@ -121,6 +184,20 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     import numpy as np
+    if args.workload == "closure":
+        res = closure_leg(gccd, workloads, torch, closure_steps=args.steps, exact_steps=2)
+        if res is None:
+            print("bench.py: no trained closure weights in the package", file=sys.stderr)
+            return 1
+        c = res["closure"]
+        print(json.dumps({
+            "metric": "carrier-steps/s of the far-field closure at 1 GPU (exact vs closure)",
+            "value": c["carrier_steps_per_s"], "unit": "carrier-steps/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": c["warmup"], "ms_per_step": c["ms_per_step"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32 pairs, bf16 network", "data": "synthetic",
+            "config": {"workload": res["workload"]}, "closure": res}), flush=True)
+        return 0
     if args.workload == "batch":
         events = workloads.batch_of_clouds(args.events, seed=args.seed)
         sizes = [len(e[0]) for e in events]
@@ -228,6 +305,8 @@ def main() -> int:
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = (cpu_baseline(w) if args.workload == "cloud" else
                                cpu_baseline_batch(events, w.device, w.dt_ps))
+    if args.workload == "cloud" and not args.no_closure:
+        out["closure"] = closure_leg(gccd, workloads, torch)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -1,0 +1,94 @@
+"""The trained closure against the exact path on the same GPU.
+
+The acceptance bar is the one set for the closure: cloud second moments
+within 1 % of the exact path's.  The field error is reported, with a loose
+bound (5 % rms relative to the exact field) that only catches a broken
+network or weight file; the closure's error floor from the discreteness of
+the far charges alone is 0.6-1.8 % rms at 1e5-1e4 holes (oracle, exact far
+field at the nodes).  Held-out seeds (2000 and up) only.
+"""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def g():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_11043_amd import gccd
+    return gccd
+
+
+@pytest.fixture(scope="module")
+def W():
+    from paper_2203_11043_amd import workloads
+    return workloads
+
+
+@pytest.fixture(scope="module")
+def weights():
+    from paper_2203_11043_amd import closure_eval
+    if not os.path.exists(closure_eval.WEIGHTS):
+        pytest.skip("no trained closure weights in the package")
+    return closure_eval.load_weights()
+
+
+def gpu(*arrs):
+    return [torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda() for a in arrs]
+
+
+def field(g, d, x, y, z, weights):
+    ctx = g.gccd_init(g.Params.from_device(d))
+    try:
+        if weights is not None:
+            g.gccd_set_closure(ctx, weights, 0)
+        g.gccd_load(ctx, *gpu(x, y, z))
+        return g.gccd_field(ctx, len(x)).cpu().numpy()
+    finally:
+        g.gccd_destroy(ctx)
+
+
+@pytest.mark.parametrize("n,seed", [(30000, 2001), (100000, 2002), (300000, 2003)])
+def test_closure_field_error(g, W, weights, n, seed):
+    x, y, z = W.gaussian_cloud(n, W.cloud_sigma(n), (480.0, 480.0, 250.0), seed, stream=2)
+    d = dict(W.DEVICE)
+    Ee = field(g, d, x, y, z, None)
+    Ec = field(g, d, x, y, z, weights)
+    rms = np.sqrt(np.mean(np.sum(Ee**2, axis=0)))
+    err = np.sqrt(np.mean(np.sum((Ec - Ee)**2, axis=0))) / rms
+    print(f"[closure] n={n} seed={seed}: rms field error {err:.4f} of rms |E|", flush=True)
+    assert err < 0.05
+
+
+def test_closure_run_moments(g, W, weights):
+    """A 1e5-hole cloud 30 um deep run to collection both ways: variances of
+    the collected positions within 1 %, every hole collected, same charge."""
+    n, seed = 100000, 2004
+    x, y, z = W.gaussian_cloud(n, W.cloud_sigma(n), (480.0, 480.0, 30.0), seed, stream=2)
+    d = dict(W.DEVICE, event=seed)
+    out = {}
+    for name, wt in (("exact", None), ("closure", weights)):
+        ctx = g.gccd_init(g.Params.from_device(d))
+        try:
+            if wt is not None:
+                g.gccd_set_closure(ctx, wt, 0)
+            g.gccd_load(ctx, *gpu(x, y, z))
+            done, na = g.gccd_run(ctx, 10.0, 5000)
+            pos, _ = g.gccd_positions(ctx, n)
+            st = g.gccd_stats(ctx)
+            out[name] = (pos.cpu().numpy(), done, na, st["closure_steps"])
+        finally:
+            g.gccd_destroy(ctx)
+    (pe, de, nae, _), (pc, dc, nac, cs) = out["exact"], out["closure"]
+    assert nae == 0 and nac == 0 and cs == dc
+    for a in (0, 1):
+        rel = np.var(pc[a]) / np.var(pe[a]) - 1.0
+        print(f"[closure] run n={n}: axis {a} variance exact {np.var(pe[a]):.4f} closure "
+              f"{np.var(pc[a]):.4f} rel {rel:+.2e}; steps {de} / {dc}", flush=True)
+        assert abs(rel) < 0.01
