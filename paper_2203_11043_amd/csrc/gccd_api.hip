@@ -359,7 +359,7 @@ FieldArgs field_args(const gccd_ctx* c, bool targets_all) {
 // keys[cur], count each event's travelling holes, gather the positions.
 int finish_list(gccd_ctx* c) {
     const uint32_t n = (uint32_t)c->n;
-    const uint32_t end_bit = c->kl.lbits + kMortonBits + 1 + c->kl.ebits;
+    const uint32_t end_bit = c->kl.lbits + kCurveBits + 1 + c->kl.ebits;
     GCCD_HIP(c, sort_keys(c->sort_tmp, c->sort_tmp_bytes, c->keys[c->cur ^ 1], c->keys[c->cur], n,
                           end_bit, c->stream));
     GCCD_HIP(c, launch_fill_u32(c->meta + kMetaPending, 4, 0u, c->stream));
@@ -438,15 +438,16 @@ bool closure_applies(const gccd_ctx* c) {
            c->p.collected_are_sources && c->n >= c->closure_min;
 }
 
-// Source chunks of the near sum: enough workgroups to fill the chip, at least
-// 4 candidate tiles per chunk, at most 32.
+// Source chunks of the near sum: as many as allowed (at least 4 candidate
+// tiles per chunk, at most 32).  The near work of a target block varies by
+// orders of magnitude (dense centre against sparse edge, and blocks whose
+// box spans a jump of the spatial order see most tiles as near), so the
+// split is chosen for the longest blocks, not to fill the chip: a chunk
+// that finds no tile near costs only the scan of its candidates.
 void choose_near_chunks(gccd_ctx* c) {
-    const uint64_t blocks = ((uint64_t)c->n + kFieldThreads - 1) / kFieldThreads;
     const uint64_t tiles = ((uint64_t)c->n + kTile - 1) / kTile;
-    uint64_t s = ((uint64_t)c->n_cu * 48 + blocks - 1) / blocks;
-    s = std::min<uint64_t>(s, std::max<uint64_t>(1, tiles / 4));
-    s = std::min<uint64_t>(s, 32);
-    c->near_chunks = (int)std::max<uint64_t>(s, 1);
+    const uint64_t s = std::min<uint64_t>(32, std::max<uint64_t>(1, tiles / 4));
+    c->near_chunks = (int)s;
 }
 
 // part holds the near chunks plus one group for the far field; the item
@@ -703,7 +704,8 @@ int gccd_load_events(gccd_ctx* c, int32_t n_events, const int64_t* offsets, cons
               hipMalloc(&c->keys[1], (size_t)n * sizeof(uint64_t)) == hipSuccess &&
               hipMalloc(&c->ps[0], d) == hipSuccess && hipMalloc(&c->ps[1], d) == hipSuccess &&
               hipMalloc(&c->ps[2], d) == hipSuccess &&
-              hipMalloc(&c->tile_box, 6 * sizeof(double) * tile_event.size()) == hipSuccess &&
+              hipMalloc(&c->tile_box, kBoxRows * sizeof(double) * tile_event.size()) ==
+                  hipSuccess &&
               hipMalloc(&c->ev_off_d, (E + 1) * sizeof(uint32_t)) == hipSuccess &&
               hipMalloc(&c->ev_tile_d, (E + 1) * sizeof(uint32_t)) == hipSuccess &&
               hipMalloc(&c->tile_event_d, tile_event.size() * sizeof(uint32_t)) == hipSuccess &&
@@ -715,7 +717,7 @@ int gccd_load_events(gccd_ctx* c, int32_t n_events, const int64_t* offsets, cons
         return fail(c, GCCD_E_NOMEM, "gccd_load_events: device allocation failed");
     }
     size_t need = 0;
-    GCCD_HIP(c, sort_keys_storage((uint32_t)n, kl.lbits + kMortonBits + 1 + kl.ebits, &need));
+    GCCD_HIP(c, sort_keys_storage((uint32_t)n, kl.lbits + kCurveBits + 1 + kl.ebits, &need));
     if (hipMalloc(&c->sort_tmp, std::max<size_t>(need, 1)) != hipSuccess) {
         free_buffers(c);
         return fail(c, GCCD_E_NOMEM, "gccd_load_events: sort storage allocation failed");

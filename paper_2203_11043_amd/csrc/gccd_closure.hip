@@ -168,13 +168,20 @@ hipError_t launch_grid_params(const double* part, const double* x, const double*
 // ---------------------------------------------------------------------------
 // Cloud-in-cell deposit in 32.32 fixed point: integer atomics make the sum
 // independent of their order.  The charges come in the spatially sorted slot
-// order, so a wave's 64 charges usually share one cell; the wave then adds
-// its 8 corner weights first and issues 8 atomics instead of 512.
+// order, so a workgroup's 256 charges touch only a few nodes: they are
+// added first into an 8x8x8 window of nodes in LDS (64-bit LDS atomics)
+// and the window's non-zero nodes then go to the grid with one global atomic
+// each.  A workgroup whose charges span more than the window (sparse edges
+// of a cloud) adds its weights to the grid directly.
 // ---------------------------------------------------------------------------
+constexpr int kWin = 8;
+
 __global__ __launch_bounds__(256) void deposit_cic(const double* px, const double* py,
                                                    const double* pz, uint32_t n,
                                                    const GridParams* gp,
                                                    unsigned long long* acc) {
+    __shared__ unsigned long long win[kWin * kWin * kWin];
+    __shared__ int red[6][4];
     const double inv_h = gp->inv_h;
     const double o[3] = {gp->origin[0], gp->origin[1], gp->origin[2]};
     const uint32_t j = blockIdx.x * 256u + threadIdx.x;
@@ -203,30 +210,59 @@ __global__ __launch_bounds__(256) void deposit_cic(const double* px, const doubl
         const double wz = (k & 4) ? f[2] : 1.0 - f[2];
         w[k] = valid ? (unsigned long long)__double2ll_rn(wx * wy * wz * 4294967296.0) : 0ull;
     }
-    const int c = (cell[2] * kGrid + cell[1]) * kGrid + cell[0];
-    const uint64_t vmask = __ballot(valid);
-    if (vmask == 0ull) return;  // the whole wave is past the end
-    const int src = __ffsll((unsigned long long)vmask) - 1;
-    const int c0 = __shfl(c, src);
-    const bool same = __ballot(valid && c != c0) == 0ull;
-    const int lane = threadIdx.x & 63;
-    if (same) {
-        // every valid lane shares one cell: add the weights over the wave
+    // the workgroup's cell range per axis
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int lo[3], hi[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = valid ? cell[d] : kGrid;
+        hi[d] = valid ? cell[d] : -1;
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) {
+            lo[d] = min(lo[d], __shfl_xor(lo[d], m));
+            hi[d] = max(hi[d], __shfl_xor(hi[d], m));
+        }
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            red[d][wave] = lo[d];
+            red[3 + d][wave] = hi[d];
+        }
+    }
+    for (int i = threadIdx.x; i < kWin * kWin * kWin; i += 256) win[i] = 0ull;
+    __syncthreads();
+    bool fits = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = min(min(red[d][0], red[d][1]), min(red[d][2], red[d][3]));
+        hi[d] = max(max(red[3 + d][0], red[3 + d][1]), max(red[3 + d][2], red[3 + d][3]));
+        fits = fits && hi[d] + 1 - lo[d] < kWin;  // nodes lo .. hi + 1
+    }
+    if (!fits) {
+        if (!valid) return;
+        const int c = (cell[2] * kGrid + cell[1]) * kGrid + cell[0];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            unsigned long long v = w[k];
-#pragma unroll
-            for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
-            w[k] = v;
+            const int node = c + ((k & 4) ? kGrid * kGrid : 0) + ((k & 2) ? kGrid : 0) + (k & 1);
+            atomicAdd(&acc[node], w[k]);
         }
-        if (lane != src) return;
-    } else if (!valid) {
         return;
     }
+    if (valid) {
+        const int c = ((cell[2] - lo[2]) * kWin + (cell[1] - lo[1])) * kWin + (cell[0] - lo[0]);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const int node = c + ((k & 4) ? kGrid * kGrid : 0) + ((k & 2) ? kGrid : 0) + (k & 1);
-        atomicAdd(&acc[node], w[k]);
+        for (int k = 0; k < 8; ++k) {
+            const int node = c + ((k & 4) ? kWin * kWin : 0) + ((k & 2) ? kWin : 0) + (k & 1);
+            atomicAdd(&win[node], w[k]);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kWin * kWin * kWin; i += 256) {
+        const unsigned long long v = win[i];
+        if (v == 0ull) continue;
+        const int x = lo[0] + i % kWin, y = lo[1] + (i / kWin) % kWin, z = lo[2] + i / (kWin * kWin);
+        if (x < kGrid && y < kGrid && z < kGrid) atomicAdd(&acc[(z * kGrid + y) * kGrid + x], v);
     }
 }
 

@@ -9,17 +9,18 @@ namespace gccd {
 constexpr int kFieldThreads = 256;   // threads per Eq. (6) workgroup (4 wave64)
 constexpr int kTile = 256;           // sources staged in LDS per tile
 constexpr int kMaxChunks = 64;       // largest source split of one target's sum
+constexpr int kBoxRows = 30;         // per source tile: its box, then its four quarters' boxes
 constexpr int kStepThreads = 256;
 
 // Carrier lists hold one 64-bit key per carrier:
-//   [event | collected | 36-bit Morton code of the 0.25 um cell | local index]
+//   [event | collected | 36-bit Hilbert index of the 0.25 um cell | local index]
 // with the local index (within its event) in the low lbits bits and the
 // event in the top ebits bits (ebits + lbits <= 27).  Keys are unique, so
 // sorting them is deterministic; the sorted list is one segment per event,
 // in event order, each holding its travelling holes first and each part in
 // spatial order, so nearby holes share workgroups and source tiles.
-constexpr double kCellPerUm = 4.0;     // Morton cells of 0.25 um
-constexpr int kMortonBits = 36;        // 12 bits per axis (wraps every 1024 um)
+constexpr double kCellPerUm = 4.0;     // cells of 0.25 um along the curve
+constexpr int kCurveBits = 36;         // 12 bits per axis (wraps every 1024 um)
 constexpr int kMaxKeyPayload = 27;     // ebits + lbits
 
 struct KeyLayout {
@@ -46,7 +47,7 @@ struct FieldArgs {
     const double* px;           // positions in list-slot order (gathered)
     const double* py;
     const double* pz;
-    const double* tile_box;     // [6][tile_stride] boxes of the source tiles
+    const double* tile_box;     // [kBoxRows][tile_stride] boxes of the source tiles
     uint32_t tile_stride;
     float eps2;                 // softening length squared, um^2
     double eps2d;               // the same in FP64 (FP64 mode)

@@ -16,30 +16,56 @@ namespace gccd {
 
 // ---------------------------------------------------------------------------
 // Keys.  A hole's 0.25 um cell (12 bits per axis, wrapping every 1024 um) is
-// interleaved bit by bit into a 36-bit Morton code.
+// mapped to its 36-bit index along a 3D Hilbert curve, which visits
+// face-adjacent cells one after the other: a run of consecutive keys is a
+// compact region with no jumps, so source tiles and target blocks have small
+// bounding boxes.  The index follows Skilling's transposition (J. Skilling,
+// "Programming the Hilbert curve", AIP Conf. Proc. 707, 381 (2004)): undo
+// the excess work axis by axis from the top bit down, Gray-encode, and
+// interleave the bits of the transposed coordinates (x first in each triple).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t cell12(double v) {
     if (!isfinite(v)) return 0u;
     return (uint32_t)(int64_t)floor(v * kCellPerUm) & 0xFFFu;
 }
 
-__device__ __forceinline__ uint64_t morton36(uint32_t cx, uint32_t cy, uint32_t cz) {
-    uint64_t m = 0;
+__device__ __forceinline__ uint64_t hilbert36(uint32_t cx, uint32_t cy, uint32_t cz) {
+    uint32_t X[3] = {cx, cy, cz};
 #pragma unroll
-    for (int b = 0; b < 12; ++b) {
-        m |= (uint64_t)((cx >> b) & 1u) << (3 * b);
-        m |= (uint64_t)((cy >> b) & 1u) << (3 * b + 1);
-        m |= (uint64_t)((cz >> b) & 1u) << (3 * b + 2);
+    for (uint32_t Q = 1u << 11; Q > 1u; Q >>= 1) {
+        const uint32_t P = Q - 1u;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const bool set = (X[i] & Q) != 0u;
+            const uint32_t t = set ? 0u : ((X[0] ^ X[i]) & P);  // exchange low bits
+            X[0] ^= (set ? P : 0u) ^ t;                          // or invert them
+            X[i] ^= t;
+        }
     }
-    return m;
+    X[1] ^= X[0];
+    X[2] ^= X[1];
+    uint32_t t = 0u;
+#pragma unroll
+    for (uint32_t Q = 1u << 11; Q > 1u; Q >>= 1)
+        if (X[2] & Q) t ^= Q - 1u;
+    X[0] ^= t;
+    X[1] ^= t;
+    X[2] ^= t;
+    uint64_t key = 0;
+#pragma unroll
+    for (int j = 11; j >= 0; --j) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) key = (key << 1) | (uint64_t)((X[i] >> j) & 1u);
+    }
+    return key;
 }
 
 __device__ __forceinline__ uint64_t make_key(uint32_t event, bool collected, double x, double y,
                                              double z, uint32_t local, KeyLayout kl) {
     uint64_t k = (uint64_t)local;
-    k |= morton36(cell12(x), cell12(y), cell12(z)) << kl.lbits;
-    if (collected) k |= 1ull << (kl.lbits + kMortonBits);
-    k |= (uint64_t)event << (kl.lbits + kMortonBits + 1);
+    k |= hilbert36(cell12(x), cell12(y), cell12(z)) << kl.lbits;
+    if (collected) k |= 1ull << (kl.lbits + kCurveBits);
+    k |= (uint64_t)event << (kl.lbits + kCurveBits + 1);
     return k;
 }
 
@@ -48,11 +74,11 @@ __device__ __forceinline__ uint32_t key_local(uint64_t k, KeyLayout kl) {
 }
 
 __device__ __forceinline__ uint32_t key_event(uint64_t k, KeyLayout kl) {
-    return (uint32_t)(k >> (kl.lbits + kMortonBits + 1));
+    return (uint32_t)(k >> (kl.lbits + kCurveBits + 1));
 }
 
 __device__ __forceinline__ bool key_collected(uint64_t k, KeyLayout kl) {
-    return ((k >> (kl.lbits + kMortonBits)) & 1ull) != 0ull;
+    return ((k >> (kl.lbits + kCurveBits)) & 1ull) != 0ull;
 }
 
 // event of carrier i: the last e with ev_off[e] <= i (binary search)
@@ -574,7 +600,7 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles_f64(FieldArgs a) {
 __global__ __launch_bounds__(kFieldThreads) void near_tiles(FieldArgs a, const GridParams* gp) {
     __shared__ __align__(16) float sh[2][6][kTile];
     __shared__ double box[6][kFieldThreads / 64];
-    __shared__ double tbox[2][6];
+    __shared__ double tbox[2][kBoxRows];  // the staged tile's box and its quarters' boxes
     __shared__ uint32_t list[kFieldThreads];
     __shared__ uint32_t wcount[kFieldThreads / 64];
 
@@ -611,6 +637,9 @@ __global__ __launch_bounds__(kFieldThreads) void near_tiles(FieldArgs a, const G
     hi_x = wave_max(hi_x);
     hi_y = wave_max(hi_y);
     hi_z = wave_max(hi_z);
+    // this wave's own 64 targets, for culling source quarters
+    const double wl_x = uniform(lo_x), wl_y = uniform(lo_y), wl_z = uniform(lo_z);
+    const double wh_x = uniform(hi_x), wh_y = uniform(hi_y), wh_z = uniform(hi_z);
     if (lane == 0) {
         box[0][wave] = lo_x;
         box[1][wave] = lo_y;
@@ -665,10 +694,10 @@ __global__ __launch_bounds__(kFieldThreads) void near_tiles(FieldArgs a, const G
             qy = a.py[off + i];
             qz = a.pz[off + i];
         }
-        if (tid < 6) qb = a.tile_box[(size_t)tid * a.tile_stride + tile0 + t];
+        if (tid < kBoxRows) qb = a.tile_box[(size_t)tid * a.tile_stride + tile0 + t];
     };
     auto stage = [&](int b) {
-        if (tid < 6) tbox[b][tid] = qb;
+        if (tid < kBoxRows) tbox[b][tid] = qb;
         const double rx = qx - ox, ry = qy - oy, rz = qz - oz;
         const float fx = (float)rx, fy = (float)ry, fz = (float)rz;
         sh[b][0][tid] = fx;
@@ -721,38 +750,50 @@ __global__ __launch_bounds__(kFieldThreads) void near_tiles(FieldArgs a, const G
             if (more) fetch(list[q + 1]);
             const uint32_t cnt = min((uint32_t)kTile, ns - tt * kTile);
             float bx[1] = {0.0f}, by[1] = {0.0f}, bz[1] = {0.0f};
-            const float* hxp = sh[buf][0];
-            const float* hyp = sh[buf][1];
-            const float* hzp = sh[buf][2];
-            const float* lxp = sh[buf][3];
-            const float* lyp = sh[buf][4];
-            const float* lzp = sh[buf][5];
             const double* tb = tbox[buf];
-            const double gx = fmax(0.0, fmax(tb[0] - hi_x, lo_x - tb[3]));
-            const double gy = fmax(0.0, fmax(tb[1] - hi_y, lo_y - tb[4]));
-            const double gz = fmax(0.0, fmax(tb[2] - hi_z, lo_z - tb[5]));
-            const bool far_tile = gx * gx + gy * gy + gz * gz >= rc2d;
-            // largest distance between the two boxes: every pair well inside a
-            // (a margin far above the FP32 error of r^2) needs no per-pair test
-            const double mx = fmax(tb[3] - lo_x, hi_x - tb[0]);
-            const double my = fmax(tb[4] - lo_y, hi_y - tb[1]);
-            const double mz = fmax(tb[5] - lo_z, hi_z - tb[2]);
-            const bool inside = mx * mx + my * my + mz * mz < 0.9999 * a2;
-            if (inside) {
-                if (far_tile)
-                    tile_terms<1, kDiffHi, false>(hxp, hyp, hzp, lxp, lyp, lzp, cnt, thx, thy, thz,
-                                                  tlx, tly, tlz, a.eps2, rc2, bx, by, bz);
-                else
-                    tile_terms<1, kDiffNear, false>(hxp, hyp, hzp, lxp, lyp, lzp, cnt, thx, thy,
-                                                    thz, tlx, tly, tlz, a.eps2, rc2, bx, by, bz);
-            } else {
-                if (far_tile)
-                    tile_terms<1, kDiffHi, true>(hxp, hyp, hzp, lxp, lyp, lzp, cnt, thx, thy, thz,
-                                                 tlx, tly, tlz, a.eps2, rc2, bx, by, bz, cut2);
-                else
-                    tile_terms<1, kDiffNear, true>(hxp, hyp, hzp, lxp, lyp, lzp, cnt, thx, thy,
-                                                   thz, tlx, tly, tlz, a.eps2, rc2, bx, by, bz,
-                                                   cut2);
+            // each wave takes the quarters of the tile within a of its own targets
+#pragma unroll
+            for (int qd = 0; qd < kTile / 64; ++qd) {
+                const uint32_t k0 = (uint32_t)qd * 64u;
+                if (k0 >= cnt) break;
+                const uint32_t kn = min(64u, cnt - k0);
+                const double* qb6 = tb + 6 + qd;  // bound k of this quarter at qb6[4 k]
+                const double gx = fmax(0.0, fmax(qb6[0] - wh_x, wl_x - qb6[12]));
+                const double gy = fmax(0.0, fmax(qb6[4] - wh_y, wl_y - qb6[16]));
+                const double gz = fmax(0.0, fmax(qb6[8] - wh_z, wl_z - qb6[20]));
+                const double gap2 = gx * gx + gy * gy + gz * gz;
+                if (!(gap2 < a2)) continue;
+                const bool far_q = gap2 >= rc2d;
+                // largest distance between the boxes: every pair well inside a
+                // (a margin far above the FP32 error of r^2) needs no per-pair test
+                const double mx = fmax(qb6[12] - wl_x, wh_x - qb6[0]);
+                const double my = fmax(qb6[16] - wl_y, wh_y - qb6[4]);
+                const double mz = fmax(qb6[20] - wl_z, wh_z - qb6[8]);
+                const bool inside = mx * mx + my * my + mz * mz < 0.9999 * a2;
+                const float* hxp = sh[buf][0] + k0;
+                const float* hyp = sh[buf][1] + k0;
+                const float* hzp = sh[buf][2] + k0;
+                const float* lxp = sh[buf][3] + k0;
+                const float* lyp = sh[buf][4] + k0;
+                const float* lzp = sh[buf][5] + k0;
+                if (inside) {
+                    if (far_q)
+                        tile_terms<1, kDiffHi, false>(hxp, hyp, hzp, lxp, lyp, lzp, kn, thx, thy,
+                                                      thz, tlx, tly, tlz, a.eps2, rc2, bx, by, bz);
+                    else
+                        tile_terms<1, kDiffNear, false>(hxp, hyp, hzp, lxp, lyp, lzp, kn, thx, thy,
+                                                        thz, tlx, tly, tlz, a.eps2, rc2, bx, by,
+                                                        bz);
+                } else {
+                    if (far_q)
+                        tile_terms<1, kDiffHi, true>(hxp, hyp, hzp, lxp, lyp, lzp, kn, thx, thy,
+                                                     thz, tlx, tly, tlz, a.eps2, rc2, bx, by, bz,
+                                                     cut2);
+                    else
+                        tile_terms<1, kDiffNear, true>(hxp, hyp, hzp, lxp, lyp, lzp, kn, thx, thy,
+                                                       thz, tlx, tly, tlz, a.eps2, rc2, bx, by, bz,
+                                                       cut2);
+                }
             }
             ax[0] += bx[0];
             ay[0] += by[0];
@@ -878,7 +919,9 @@ hipError_t launch_count(const uint64_t* keys, const uint32_t* ev_off, uint32_t n
 
 // One workgroup per source tile g of event e = tile_event[g] (local tile
 // t = g - ev_tile[e]): positions of every slot of the tile, bounding box of
-// the slots that are sources.
+// the slots that are sources (rows 0-5 of box: low x, y, z, high x, y, z),
+// and the same for each 64-slot quarter of the tile (row 6 + 4 k + q for
+// bound k of quarter q), which the near-field kernel culls by.
 __global__ __launch_bounds__(kTile) void gather_tiles(
     const uint64_t* keys, const uint32_t* ev_off, const uint32_t* ev_tile,
     const uint32_t* tile_event, const uint32_t* ev_active, int sources_all, KeyLayout kl,
@@ -921,6 +964,9 @@ __global__ __launch_bounds__(kTile) void gather_tiles(
         red[3][wave] = hx;
         red[4][wave] = hy;
         red[5][wave] = hz;
+        const double v[6] = {lx, ly, lz, hx, hy, hz};
+#pragma unroll
+        for (int k = 0; k < 6; ++k) box[(size_t)(6 + 4 * k + wave) * stride + g] = v[k];
     }
     __syncthreads();
     if (threadIdx.x < 6) {

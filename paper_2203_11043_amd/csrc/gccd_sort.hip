@@ -1,4 +1,4 @@
-// Radix sort of the 64-bit Morton/index keys that order the Eq. (6)
+// Radix sort of the 64-bit curve/index keys that order the Eq. (6)
 // targets spatially (rocPRIM device radix sort; temporary storage is
 // allocated once per load by the caller, so a step allocates nothing).
 #include "gccd_internal.h"
