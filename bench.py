@@ -168,6 +168,9 @@ def main() -> int:
     ap.add_argument("--tpt", type=int, default=0, help="targets per thread (0 = auto)")
     ap.add_argument("--chunks", type=int, default=0, help="source chunks (0 = auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batch workload: keep the automatic launch shape instead of "
+                         "measuring the candidates first (gccd_autotune)")
     ap.add_argument("--no-closure", action="store_true",
                     help="skip the closure-versus-exact leg on the 1e6-hole cloud")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -218,8 +221,11 @@ def main() -> int:
     ctx = gccd.gccd_init(params)
     gccd.gccd_set_launch(ctx, args.tpt, args.chunks)
     xs = [torch.as_tensor(v).cuda() for v in (w.x, w.y, w.z)]
+    tuned = None
     if args.workload == "batch":
         gccd.gccd_load_events(ctx, offsets, *xs)
+        if not args.no_autotune and not (args.tpt or args.chunks):
+            tuned = gccd.gccd_autotune(ctx)
 
         def step():
             gccd.gccd_run(ctx, w.dt_ps, 1)
@@ -285,6 +291,9 @@ def main() -> int:
             "targets_per_thread": s1["targets_per_thread"],
             "source_chunks": s1["source_chunks"],
             "max_source_chunks": s1["max_source_chunks"],
+            "launch_shape": ("autotuned: targets per thread %d, source chunks %s (%.2f ms)"
+                             % (tuned[0], tuned[1] or "automatic", tuned[2])) if tuned else
+                            ("fixed" if (args.tpt or args.chunks) else "automatic"),
         },
         "carrier_steps_per_s": csteps / elapsed,
         "pct_fp32_peak": 100.0 * FLOP_PER_PAIR * pair_rate / (PEAK_FP32_TFLOPS * 1e12),

@@ -171,12 +171,26 @@ int gccd_stats(gccd_ctx* c, gccd_stats_t* out);
 
 /* Fixes the launch shape of the Eq. (6) kernel: targets per thread (1, 2 or
  * 4) and the number of source chunks each target's sum is split into (1-64,
- * the same for every event).  0 for either means "choose automatically" (the
+ * the same for every event, at most the event's tile count of 256 sources).  0 for either means "choose automatically" (the
  * default).  The split changes the FP32 summation order; the targets per
  * thread change the workgroups' origins and so the rounding of the pair
  * differences.  Applies to the current load and later ones; synchronises the
  * stream.  GCCD_E_INVALID outside those ranges. */
 int gccd_set_launch(gccd_ctx* c, int32_t targets_per_thread, int32_t source_chunks);
+
+/* Picks the launch shape of gccd_set_launch by measurement: times the
+ * Eq. (6) launch of the loaded state (its travelling holes against their
+ * sources) for targets per thread 1, 2, 4 and source chunks 0 (automatic),
+ * 4, 8, 16, 24, 32, 48, 64 (capped per event at its tile count), the median
+ * of three launches each after one untimed, and keeps the fastest for this
+ * load and later ones, as gccd_set_launch would.  About 100 launches: call
+ * it once per workload.  The shape changes the FP32 summation order, so
+ * results are reproducible across processes only for a fixed shape: the
+ * chosen values (any pointer may be NULL) can be passed to gccd_set_launch.
+ * Without Coulomb repulsion or travelling holes nothing is timed and the
+ * current shape stays.  Synchronises the stream.  GCCD_E_STATE before load. */
+int gccd_autotune(gccd_ctx* c, int32_t* targets_per_thread, int32_t* source_chunks,
+                  double* ms_per_launch);
 
 /* Arithmetic of the Eq. (6) pair sum.  The paper keeps positions as single
  * precision floats and gives no error analysis; these modes measure what

@@ -241,7 +241,8 @@ void choose_chunks(gccd_ctx* c) {
         const uint64_t tiles = (ne + kTile - 1) / kTile;
         uint64_t s;
         if (c->chunks_fixed) {
-            s = (uint64_t)c->chunks_fixed;
+            // at most one chunk per tile: small events of a batch get no empty chunks
+            s = std::min<uint64_t>((uint64_t)c->chunks_fixed, std::max<uint64_t>(1, tiles));
         } else {
             s = std::max<uint64_t>((ne + 3071) / 3072, (want + tblocks - 1) / tblocks);
             s = std::min<uint64_t>(s, std::max<uint64_t>(1, tiles / 4));
@@ -894,6 +895,72 @@ int gccd_closure_parts(gccd_ctx* c, double* near_x, double* near_y, double* near
     GCCD_HIP(c, hipMemcpyAsync(grid, c->gp, 4 * sizeof(double), hipMemcpyDeviceToDevice,
                                c->stream));
     GCCD_HIP(c, hipStreamSynchronize(c->stream));
+    return GCCD_OK;
+}
+
+int gccd_autotune(gccd_ctx* c, int32_t* targets_per_thread, int32_t* source_chunks,
+                  double* ms_per_launch) {
+    if (!c) return GCCD_E_INVALID;
+    if (!c->loaded) return fail(c, GCCD_E_STATE, "gccd_autotune before gccd_load");
+    GCCD_HIP(c, hipStreamSynchronize(c->stream));
+    double best_ms = -1.0;
+    int best_t = c->tpt_fixed, best_s = c->chunks_fixed;
+    if (c->list_mode && c->n_active > 0) {
+        hipEvent_t e0, e1;
+        GCCD_HIP(c, hipEventCreate(&e0));
+        GCCD_HIP(c, hipEventCreate(&e1));
+        static const int kT[3] = {1, 2, 4};
+        static const int kS[8] = {0, 4, 8, 16, 24, 32, 48, 64};
+        int r = GCCD_OK;
+        for (int ti = 0; ti < 3 && r == GCCD_OK; ++ti)
+            for (int si = 0; si < 8 && r == GCCD_OK; ++si) {
+                c->tpt_fixed = kT[ti];
+                c->chunks_fixed = kS[si];
+                c->tpt = kT[ti];
+                choose_chunks(c);
+                r = size_chunk_buffers(c);
+                if (r == GCCD_OK) r = build_items(c, c->host_active);
+                if (r != GCCD_OK) break;
+                FieldArgs fa = field_args(c, false);
+                float t[3];
+                for (int rep = 0; rep < 4 && r == GCCD_OK; ++rep) {  // one untimed, three timed
+                    if (hipEventRecord(e0, c->stream) != hipSuccess ||
+                        launch_field(fa, c->tpt, c->precision, c->n_items, c->stream) !=
+                            hipSuccess ||
+                        hipEventRecord(e1, c->stream) != hipSuccess ||
+                        hipEventSynchronize(e1) != hipSuccess)
+                        r = fail(c, GCCD_E_DEVICE, "gccd_autotune: timed launch failed");
+                    else if (rep > 0 && hipEventElapsedTime(&t[rep - 1], e0, e1) != hipSuccess)
+                        r = fail(c, GCCD_E_DEVICE, "gccd_autotune: event timing failed");
+                }
+                if (r != GCCD_OK) break;
+                std::sort(t, t + 3);
+                if (best_ms < 0.0 || t[1] < best_ms) {
+                    best_ms = t[1];
+                    best_t = kT[ti];
+                    best_s = kS[si];
+                }
+            }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (r != GCCD_OK) {
+            free_buffers(c);
+            return r;
+        }
+    }
+    // keep the fastest shape for this load and later ones
+    c->tpt_fixed = best_t;
+    c->chunks_fixed = best_s;
+    c->tpt = best_t ? best_t : 1;
+    choose_chunks(c);
+    int r = size_chunk_buffers(c);
+    if (r != GCCD_OK) {
+        free_buffers(c);
+        return r;
+    }
+    if (targets_per_thread) *targets_per_thread = c->tpt;
+    if (source_chunks) *source_chunks = best_s;
+    if (ms_per_launch) *ms_per_launch = best_ms;
     return GCCD_OK;
 }
 

@@ -37,8 +37,9 @@ PRECISION_MODES = {"default": 0, "block": 1, "event": 2, "absolute": 3, "compens
 # every symbol the header declares
 EXPORTS = ("gccd_init", "gccd_load", "gccd_load_events", "gccd_run", "gccd_image",
            "gccd_image_events", "gccd_field", "gccd_positions", "gccd_stats",
-           "gccd_set_launch", "gccd_set_precision", "gccd_set_closure", "gccd_closure_parts",
-           "gccd_set_timing", "gccd_strerror", "gccd_last_error", "gccd_destroy")
+           "gccd_set_launch", "gccd_autotune", "gccd_set_precision", "gccd_set_closure",
+           "gccd_closure_parts", "gccd_set_timing", "gccd_strerror", "gccd_last_error",
+           "gccd_destroy")
 
 
 class CParams(ctypes.Structure):
@@ -97,6 +98,8 @@ def _load():
     L.gccd_stats.argtypes = [P, ctypes.POINTER(CStats)]
     L.gccd_set_launch.argtypes = [P, i32, i32]
     L.gccd_set_precision.argtypes = [P, i32]
+    L.gccd_autotune.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                ctypes.POINTER(d)]
     L.gccd_set_closure.argtypes = [P, P, i64, i64]
     L.gccd_closure_parts.argtypes = [P, P, P, P, P, P, P, P, P]
     L.gccd_set_timing.argtypes = [P, i32]
@@ -283,6 +286,14 @@ def gccd_stats(ctx: int) -> dict:
 
 def gccd_set_launch(ctx: int, targets_per_thread: int = 0, source_chunks: int = 0) -> None:
     _check(ctx, lib.gccd_set_launch(ctx, int(targets_per_thread), int(source_chunks)))
+
+
+def gccd_autotune(ctx: int):
+    """Returns (targets_per_thread, source_chunks, ms_per_launch) of the
+    fastest measured launch shape, which the context keeps."""
+    t, s, ms = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_double(0.0)
+    _check(ctx, lib.gccd_autotune(ctx, ctypes.byref(t), ctypes.byref(s), ctypes.byref(ms)))
+    return t.value, s.value, ms.value
 
 
 def gccd_set_precision(ctx: int, mode) -> None:

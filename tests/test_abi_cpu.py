@@ -29,7 +29,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported(g):
     names = declared_functions()
-    assert len(names) == 17
+    assert len(names) == 18
     for name in names:
         assert hasattr(g.lib, name), name
     assert sorted(g.EXPORTS) == names
@@ -107,6 +107,7 @@ def test_null_arguments(g):
     assert L.gccd_set_timing(None, 1) == g.GCCD_E_INVALID
     assert L.gccd_set_precision(None, 0) == g.GCCD_E_INVALID
     assert L.gccd_set_closure(None, None, 0, 0) == g.GCCD_E_INVALID
+    assert L.gccd_autotune(None, None, None, None) == g.GCCD_E_INVALID
     assert L.gccd_closure_parts(None, None, None, None, None, None, None, None, None) == \
         g.GCCD_E_INVALID
     L.gccd_destroy(None)

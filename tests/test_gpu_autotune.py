@@ -1,0 +1,94 @@
+"""gccd_autotune: the measured launch shape is one of the candidates, keeps
+the field within the Eq. (6) tolerance, and reproduces bit for bit when
+fixed again with gccd_set_launch in a fresh context."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def g():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_11043_amd import gccd
+    return gccd
+
+
+@pytest.fixture(scope="module")
+def W():
+    from paper_2203_11043_amd import workloads
+    return workloads
+
+
+def gpu(*arrs):
+    return [torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda() for a in arrs]
+
+
+def test_autotune_single_cloud_and_batch(g, W, orc):
+    w = W.single_cloud(30000, seed=12, depth_um=120.0)
+    d = dict(W.DEVICE, event=4)
+    ctx = g.gccd_init(g.Params.from_device(d))
+    try:
+        g.gccd_load(ctx, *gpu(w.x, w.y, w.z))
+        tpt, chunks, ms = g.gccd_autotune(ctx)
+        print(f"[autotune] n=30000: tpt {tpt}, chunks {chunks}, {ms:.3f} ms per launch", flush=True)
+        assert tpt in (1, 2, 4) and chunks in (0, 4, 8, 16, 24, 32, 48, 64) and ms > 0
+        st = g.gccd_stats(ctx)
+        assert st["targets_per_thread"] == tpt
+        E = g.gccd_field(ctx, w.n).cpu().numpy()
+        g.gccd_run(ctx, 10.0, 20)
+        p1, _ = g.gccd_positions(ctx, w.n)
+        p1 = p1.cpu().numpy()
+    finally:
+        g.gccd_destroy(ctx)
+    idx = np.random.default_rng(3).choice(w.n, 200, replace=False)
+    Eo, A = orc.field([w.x[idx], w.y[idx], w.z[idx]], [w.x, w.y, w.z], with_magnitude=True)
+    assert np.max(np.linalg.norm(E[:, idx] - Eo, axis=0) / A) <= 1e-5
+    ctx = g.gccd_init(g.Params.from_device(d))
+    try:
+        g.gccd_set_launch(ctx, tpt, chunks)
+        g.gccd_load(ctx, *gpu(w.x, w.y, w.z))
+        g.gccd_run(ctx, 10.0, 20)
+        p2, _ = g.gccd_positions(ctx, w.n)
+        assert np.array_equal(p1, p2.cpu().numpy())
+    finally:
+        g.gccd_destroy(ctx)
+
+    # a batch of uneven events: chunks capped per event, results within tolerance
+    sizes = [300, 5000, 40, 12000, 900]
+    xs, ys, zs, off = [], [], [], [0]
+    for e, n in enumerate(sizes):
+        x, y, z = W.gaussian_cloud(n, W.cloud_sigma(n), (480.0, 480.0, 50.0 + 100 * e), 6,
+                                   stream=800 + e)
+        xs.append(x)
+        ys.append(y)
+        zs.append(z)
+        off.append(off[-1] + n)
+    x, y, z = np.concatenate(xs), np.concatenate(ys), np.concatenate(zs)
+    ctx = g.gccd_init(g.Params.from_device(d))
+    try:
+        g.gccd_load_events(ctx, off, *gpu(x, y, z))
+        tpt, chunks, ms = g.gccd_autotune(ctx)
+        print(f"[autotune] batch: tpt {tpt}, chunks {chunks}, {ms:.3f} ms", flush=True)
+        E = g.gccd_field(ctx, len(x)).cpu().numpy()
+    finally:
+        g.gccd_destroy(ctx)
+    for e in range(len(sizes)):
+        sl = slice(off[e], off[e + 1])
+        Eo, A = orc.field([x[sl], y[sl], z[sl]], with_magnitude=True)
+        ok = A > 0
+        assert np.max(np.linalg.norm(E[:, sl] - Eo, axis=0)[ok] / A[ok]) <= 1e-5, e
+
+
+def test_autotune_without_repulsion_keeps_shape(g, W):
+    ctx = g.gccd_init(g.Params.from_device(dict(W.DEVICE, coulomb=0)))
+    try:
+        g.gccd_set_launch(ctx, 2, 8)
+        g.gccd_load(ctx, *gpu(np.zeros(4), np.zeros(4), np.full(4, 5.0)))
+        tpt, chunks, ms = g.gccd_autotune(ctx)
+        assert (tpt, chunks) == (2, 8) and ms < 0
+    finally:
+        g.gccd_destroy(ctx)

@@ -101,8 +101,9 @@ def test_field_ragged_launch_shapes(g, W, orc, tpt, chunks):
     ea, er = field_errors(E, Eo, A)
     report(f"cloud n=5003 tpt={st['targets_per_thread']} chunks={st['source_chunks']}", ea, er)
     assert ea <= FIELD_TOL
-    if tpt:
-        assert st["targets_per_thread"] == tpt and st["source_chunks"] == chunks
+    if tpt:   # a fixed chunk count is capped at the event's 256-source tiles
+        assert st["targets_per_thread"] == tpt
+        assert st["source_chunks"] == min(chunks, (5003 + 255) // 256)
 
 
 @pytest.mark.parametrize("n", [30000, 100000, 300000])
