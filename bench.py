@@ -153,15 +153,82 @@ def closure_leg(gccd, workloads, torch, n: int = 1000000, seed: int = 2000,
     return out
 
 
+def sweep(gccd, workloads, torch, cpu: bool) -> dict:
+    """The paper's timing protocol (Sec. IV, Fig. 4): 10 time steps of one
+    cloud at each N, Coulomb on and off, on the GPU (median of 3 after one
+    warm-up step) and, for the CPU baseline leg, the FP64 oracle on the host
+    cores (once; Coulomb on up to N = 3e4, about 40 s in all).  Then whole
+    runs to collection of the 1000-hole cloud, a 1e4-hole cloud and the
+    muon track."""
+    import numpy as np
+    rows = []
+    for n in (100, 300, 1000, 3000, 10000, 30000, 100000, 300000):
+        w = workloads.single_cloud(n, seed=1, depth_um=300.0)
+        row = {"n": n}
+        for coulomb in (1, 0):
+            d = dict(w.device, coulomb=coulomb)
+            xs = [torch.as_tensor(v).cuda() for v in (w.x, w.y, w.z)]
+            times = []
+            for _ in range(3):
+                ctx = gccd.gccd_init(gccd.Params.from_device(d))
+                try:
+                    gccd.gccd_load(ctx, *xs)
+                    gccd.gccd_run(ctx, w.dt_ps, 1)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    gccd.gccd_run(ctx, w.dt_ps, 10)
+                    torch.cuda.synchronize()
+                    times.append(time.perf_counter() - t0)
+                finally:
+                    gccd.gccd_destroy(ctx)
+            key = "on" if coulomb else "off"
+            row[f"gpu_ms_10_steps_coulomb_{key}"] = float(np.median(times)) * 1e3
+            if cpu and (coulomb == 0 or n <= 30000):
+                import oracle
+                st = oracle.State(oracle.Device(**d), w.x, w.y, w.z)
+                t0 = time.perf_counter()
+                st.run(w.dt_ps, 10)
+                row[f"cpu_ms_10_steps_coulomb_{key}"] = (time.perf_counter() - t0) * 1e3
+                row[f"speedup_coulomb_{key}"] = (row[f"cpu_ms_10_steps_coulomb_{key}"] /
+                                                 row[f"gpu_ms_10_steps_coulomb_{key}"])
+        rows.append(row)
+    runs = []
+    for name, w in (("cloud n=1000, depth 300 um", workloads.x_ray_cloud(seed=1)),
+                    ("cloud n=10000", workloads.single_cloud(10000, seed=1)),
+                    ("muon track n=62354", workloads.muon_track(seed=1))):
+        xs = [torch.as_tensor(v).cuda() for v in (w.x, w.y, w.z)]
+        ctx = gccd.gccd_init(gccd.Params.from_device(w.device))
+        try:
+            gccd.gccd_load(ctx, *xs)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            done, na = gccd.gccd_run(ctx, w.dt_ps, 20000)
+            counts, nout = gccd.gccd_image(ctx, 0.0, 0.0, w.pitch_um, w.nx, w.ny)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            st = gccd.gccd_stats(ctx)
+        finally:
+            gccd.gccd_destroy(ctx)
+        runs.append({"workload": name, "steps": done, "travelling_at_end": na,
+                     "seconds": dt, "ms_per_step": dt / max(done, 1) * 1e3,
+                     "pair_interactions": st["pair_interactions"],
+                     "pair_interactions_per_s": st["pair_interactions"] / dt,
+                     "collected_in_grid": int(counts.sum().item()),
+                     "outside_grid": int(nout.item())})
+    return {"cpu_cores": (__import__("oracle").num_threads() if cpu else None),
+            "ten_steps": rows, "full_runs": runs}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", choices=("cloud", "batch", "closure"), default="cloud",
+    ap.add_argument("--workload", choices=("cloud", "batch", "closure", "sweep"), default="cloud",
                     help="cloud: one 1e5-hole cloud (default); batch: 4096 clouds of "
                          "200-20000 holes in one launch; closure: only the closure-versus-"
-                         "exact leg on the 1e6-hole cloud (--steps closure steps)")
+                         "exact leg on the 1e6-hole cloud (--steps closure steps); sweep: the "
+                         "paper's 10-step timing over N, Coulomb on and off, and whole runs")
     ap.add_argument("--n", type=int, default=100000)
     ap.add_argument("--events", type=int, default=4096)
     ap.add_argument("--seed", type=int, default=1)
@@ -187,6 +254,19 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     import numpy as np
+    if args.workload == "sweep":
+        res = sweep(gccd, workloads, torch, cpu=not args.no_cpu_baseline)
+        big = res["ten_steps"][-1]
+        print(json.dumps({
+            "metric": "time of 10 simulation steps against N (Coulomb on and off), 1 GPU",
+            "value": big["gpu_ms_10_steps_coulomb_on"], "unit": "ms per 10 steps at N=3e5",
+            "n_gpus": 1, "steps": 10, "warmup": 1, "ms_per_step": big["gpu_ms_10_steps_coulomb_on"] / 10,
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic", "config": {"workload": "single Gaussian clouds of 1e2-3e5 holes "
+                                                        "300 um deep; whole runs of the 1000-hole "
+                                                        "cloud, a 1e4 cloud and the muon track"},
+            "sweep": res}), flush=True)
+        return 0
     if args.workload == "closure":
         res = closure_leg(gccd, workloads, torch, closure_steps=args.steps, exact_steps=2)
         if res is None:

@@ -222,7 +222,8 @@ uint32_t bits_for(uint64_t count) {  // smallest b with 2^b >= count (0 for coun
 // still travel: every step of a load, and gccd_field, sum in the same order.
 // Enough workgroups to fill the chip (about 48 waves per SIMD in total,
 // which also evens out workgroups that meet more close pairs), at most 3072
-// sources per chunk, and at least 4 tiles per chunk.  The FP64 mode stores
+// sources per chunk, and at least one tile per chunk (a small cloud is
+// latency-bound: it gains from every extra workgroup).  The FP64 mode stores
 // each chunk's sum in two groups and so takes at most kMaxChunks / 2 chunks.
 void choose_chunks(gccd_ctx* c) {
     uint64_t tblocks = 0;
@@ -245,7 +246,7 @@ void choose_chunks(gccd_ctx* c) {
             s = std::min<uint64_t>((uint64_t)c->chunks_fixed, std::max<uint64_t>(1, tiles));
         } else {
             s = std::max<uint64_t>((ne + 3071) / 3072, (want + tblocks - 1) / tblocks);
-            s = std::min<uint64_t>(s, std::max<uint64_t>(1, tiles / 4));
+            s = std::min<uint64_t>(s, std::max<uint64_t>(1, tiles));
             s = std::max<uint64_t>(s, 1);
         }
         s = std::min<uint64_t>(s, cap);
