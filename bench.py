@@ -2,13 +2,16 @@
 
 One bench step = one simulation time step of a single 1e5-hole Gaussian
 cloud (Eq. (6) all-pairs field + drift, mobility, diffusion, FP64 update and
-collection, Sec. III.B) followed by the pixel image of the collected holes
-(Sec. V.A).  Inputs are seeded synthetic positions already resident in HBM.
+collection, Sec. III.B).  The timed steps run as the library is used: one
+gccd_run call (the host reads the counts every 32 steps), then the pixel
+image of the collected holes (Sec. V.A).  Inputs are seeded synthetic
+positions already resident in HBM.
 
 Prints one JSON line: pair-interactions/s (the headline), carrier-steps/s,
 the fraction of the FP32 vector peak, a roofline record for the Eq. (6)
-kernel timed with HIP events on the library's stream, and the FP64 CPU
-oracle timed on a bounded sample of the same workload on the host cores.
+kernel timed with HIP events on the library's stream, the FP64 CPU oracle
+timed on a bounded sample of the same workload on the host cores, and the
+far-field closure against the exact path on a 1e6-hole cloud.
 """
 from __future__ import annotations
 
@@ -97,8 +100,8 @@ def closure_leg(gccd, workloads, torch, n: int = 1000000, seed: int = 2000,
                 closure_steps: int = 10, exact_steps: int = 3) -> dict:
     """The closure against the exact path on one large cloud (width
     0.5 um (n/1000)^(1/3), 300 um deep): time per step of each, measured the
-    same way (one time step per gccd_run, warm-up first), from the same
-    positions.  The accuracy figures come from the committed evaluation of
+    same way (one gccd_run call for the timed steps, after a warm-up call),
+    from the same positions.  The accuracy figures come from the committed evaluation of
     whole runs (closure_eval.py), not from this short run."""
     import numpy as np
     from paper_2203_11043_amd import closure_eval
@@ -116,14 +119,12 @@ def closure_leg(gccd, workloads, torch, n: int = 1000000, seed: int = 2000,
             if use:
                 gccd.gccd_set_closure(ctx, weights, 0)
             gccd.gccd_load(ctx, *xs)
-            for _ in range(warm):
-                gccd.gccd_run(ctx, workloads.DT_PS, 1)
+            gccd.gccd_run(ctx, workloads.DT_PS, warm)
             torch.cuda.synchronize()
             s0 = gccd.gccd_stats(ctx)
             gccd.gccd_set_timing(ctx, True)
             t0 = time.perf_counter()
-            for _ in range(steps):
-                gccd.gccd_run(ctx, workloads.DT_PS, 1)
+            gccd.gccd_run(ctx, workloads.DT_PS, steps)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             s1 = gccd.gccd_stats(ctx)
@@ -235,6 +236,9 @@ def main() -> int:
     ap.add_argument("--tpt", type=int, default=0, help="targets per thread (0 = auto)")
     ap.add_argument("--chunks", type=int, default=0, help="source chunks (0 = auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--call-per-step", action="store_true",
+                    help="one gccd_run call and one image per time step (a host round trip "
+                         "per step) instead of one call for all timed steps")
     ap.add_argument("--no-autotune", action="store_true",
                     help="batch workload: keep the automatic launch shape instead of "
                          "measuring the candidates first (gccd_autotune)")
@@ -307,31 +311,44 @@ def main() -> int:
         if not args.no_autotune and not (args.tpt or args.chunks):
             tuned = gccd.gccd_autotune(ctx)
 
-        def step():
-            gccd.gccd_run(ctx, w.dt_ps, 1)
+        def image():
             gccd.gccd_image_events(ctx, args.events, 0.0, 0.0, w.pitch_um, w.nx, w.ny)
     else:
         gccd.gccd_load(ctx, *xs)
         counts = torch.empty((w.ny, w.nx), dtype=torch.uint32, device="cuda")
         nout = torch.empty(1, dtype=torch.uint64, device="cuda")
 
-        def step():
-            gccd.gccd_run(ctx, w.dt_ps, 1)
+        def image():
             gccd.gccd_image(ctx, 0.0, 0.0, w.pitch_um, w.nx, w.ny, counts, nout)
 
-    for _ in range(args.warmup):
-        step()
+    def run(k):
+        """k time steps, as the library is used: one gccd_run call (counts
+        polled every 32 steps), then the image of the collected holes; with
+        --call-per-step, one call and one image per step."""
+        if args.call_per_step:
+            done = 0
+            for _ in range(k):
+                done += gccd.gccd_run(ctx, w.dt_ps, 1)[0]
+                image()
+            return done
+        done = gccd.gccd_run(ctx, w.dt_ps, k)[0]
+        image()
+        return done
+
+    run(args.warmup)
     torch.cuda.synchronize()
     s0 = gccd.gccd_stats(ctx)
     gccd.gccd_set_timing(ctx, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
+    done = run(args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     s1 = gccd.gccd_stats(ctx)
     gccd.gccd_destroy(ctx)
+    if done != args.steps:
+        print(f"bench.py: only {done} of {args.steps} steps had travelling holes", file=sys.stderr)
+        return 1
 
     elapsed = t1 - t0
     pairs = s1["pair_interactions"] - s0["pair_interactions"]
@@ -366,6 +383,9 @@ def main() -> int:
             "n_holes": w.n,
             "n_events": s1["n_events"],
             "time_steps_per_step": 1,
+            "calls": ("one gccd_run and one image per step" if args.call_per_step else
+                      "one gccd_run for all timed steps (counts polled every 32 steps), "
+                      "then the image"),
             "positions": "f64",
             "pair_arithmetic": "f32 (double-single coordinate differences)",
             "targets_per_thread": s1["targets_per_thread"],
