@@ -1,11 +1,12 @@
 """The trained closure against the exact path on the same GPU.
 
 The acceptance bar is the one set for the closure: cloud second moments
-within 1 % of the exact path's.  The field error is reported, with a loose
-bound (5 % rms relative to the exact field) that only catches a broken
-network or weight file; the closure's error floor from the discreteness of
-the far charges alone is 0.6-1.8 % rms at 1e5-1e4 holes (oracle, exact far
-field at the nodes).  Held-out seeds (2000 and up) only.
+within 1 % of the exact path's.  The field error is reported relative to the
+rms of the exact far field, with a loose bound (5 %) that only catches a
+broken network or weight file; the closure's error floor from the
+discreteness of the far charges alone is 1.1 % at 3e4 holes and 0.7 % at
+1e5 (oracle, exact far field at the nodes).  Held-out seeds (2000 and up)
+only.
 """
 import os
 
@@ -56,14 +57,26 @@ def field(g, d, x, y, z, weights):
 
 @pytest.mark.parametrize("n,seed", [(30000, 2001), (100000, 2002), (300000, 2003)])
 def test_closure_field_error(g, W, weights, n, seed):
+    """Error of the closure's field against the exact path, relative to the rms
+    of the exact far field (the part the network replaces; the rms of the
+    whole field can be set by a few close pairs, which both paths sum
+    exactly)."""
     x, y, z = W.gaussian_cloud(n, W.cloud_sigma(n), (480.0, 480.0, 250.0), seed, stream=2)
     d = dict(W.DEVICE)
     Ee = field(g, d, x, y, z, None)
     Ec = field(g, d, x, y, z, weights)
-    rms = np.sqrt(np.mean(np.sum(Ee**2, axis=0)))
-    err = np.sqrt(np.mean(np.sum((Ec - Ee)**2, axis=0))) / rms
-    print(f"[closure] n={n} seed={seed}: rms field error {err:.4f} of rms |E|", flush=True)
-    assert err < 0.05
+    ctx = g.gccd_init(g.Params.from_device(d))
+    try:
+        g.gccd_load(ctx, *gpu(x, y, z))
+        near = g.gccd_closure_parts(ctx, n)[0].cpu().numpy()
+    finally:
+        g.gccd_destroy(ctx)
+    rms = lambda E: np.sqrt(np.mean(np.sum(E**2, axis=0)))
+    err_far = rms(Ec - Ee) / rms(Ee - near)
+    err_tot = rms(Ec - Ee) / rms(Ee)
+    print(f"[closure] n={n} seed={seed}: rms field error {err_far:.4f} of the rms far field "
+          f"({err_tot:.4f} of the rms field)", flush=True)
+    assert err_far < 0.05
 
 
 def test_closure_run_moments(g, W, weights):
