@@ -290,16 +290,29 @@ int size_chunk_buffers(gccd_ctx* c) {
         items += (size_t)((ne + kFieldThreads - 1) / kFieldThreads) * (size_t)c->chunks_h[e];
     }
     c->items_cap = std::max<size_t>(items, 1);
-    c->part_groups = c->max_groups;
     c->groups_mode = 0;
-    if (hipMalloc(&c->part, (size_t)c->max_groups * 3 * (size_t)c->n * sizeof(float)) !=
-            hipSuccess ||
+    // the partial sums are only needed with repulsion on (a field call on a
+    // load without it allocates them then: ensure_part)
+    c->part_groups = c->p.coulomb ? c->max_groups : 0;
+    if ((c->p.coulomb &&
+         hipMalloc(&c->part, (size_t)c->max_groups * 3 * (size_t)c->n * sizeof(float)) !=
+             hipSuccess) ||
         hipMalloc(&c->items_d, c->items_cap * sizeof(FieldItem)) != hipSuccess ||
         hipHostMalloc((void**)&c->host_items, c->items_cap * sizeof(FieldItem)) != hipSuccess)
         return fail(c, GCCD_E_NOMEM, "device allocation of the field buffers failed");
     GCCD_HIP(c, hipMemcpyAsync(c->ev_chunks_d, c->groups_h.data(), c->n_events * sizeof(int32_t),
                                hipMemcpyHostToDevice, c->stream));
     GCCD_HIP(c, hipStreamSynchronize(c->stream));
+    return GCCD_OK;
+}
+
+int ensure_part(gccd_ctx* c) {
+    if (c->part_groups >= c->max_groups) return GCCD_OK;
+    dfree(c->part);
+    if (hipMalloc(&c->part, (size_t)c->max_groups * 3 * (size_t)c->n * sizeof(float)) !=
+        hipSuccess)
+        return fail(c, GCCD_E_NOMEM, "partial-sum allocation failed");
+    c->part_groups = c->max_groups;
     return GCCD_OK;
 }
 
@@ -1122,7 +1135,8 @@ int gccd_field(gccd_ctx* c, double* ex, double* ey, double* ez) {
         if (r == GCCD_OK) r = closure_field(c, true, n, true);
         if (r != GCCD_OK) return r;
     } else {
-        int r = set_groups(c, 0);
+        int r = ensure_part(c);
+        if (r == GCCD_OK) r = set_groups(c, 0);
         if (r != GCCD_OK) return r;
         std::vector<uint32_t> all(c->n_events);
         for (uint32_t e = 0; e < c->n_events; ++e) all[e] = c->off_h[e + 1] - c->off_h[e];
