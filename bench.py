@@ -387,7 +387,11 @@ def main() -> int:
                       "one gccd_run for all timed steps (counts polled every 32 steps), "
                       "then the image"),
             "positions": "f64",
-            "pair_arithmetic": "f32 (double-single coordinate differences)",
+            "pair_arithmetic": ("f32, origin per workgroup; far tiles in the expanded-square form, "
+                                "pairs closer than rho/4 with double-single differences"
+                                if s1["targets_per_thread"] == 1 else
+                                "f32, origin per workgroup; pairs closer than rho/4 with "
+                                "double-single differences"),
             "targets_per_thread": s1["targets_per_thread"],
             "source_chunks": s1["source_chunks"],
             "max_source_chunks": s1["max_source_chunks"],
@@ -399,7 +403,8 @@ def main() -> int:
         "pct_fp32_peak": 100.0 * FLOP_PER_PAIR * pair_rate / (PEAK_FP32_TFLOPS * 1e12),
         "roofline": {
             "bound": "alu",
-            "kernel": "field_tiles (Eq. (6))",
+            "kernel": ("field_tiles_expanded (Eq. (6))" if s1["targets_per_thread"] == 1
+                       else "field_tiles<%d> (Eq. (6))" % s1["targets_per_thread"]),
             "achieved": kern_tflops,
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",

@@ -171,19 +171,26 @@ int gccd_stats(gccd_ctx* c, gccd_stats_t* out);
 
 /* Fixes the launch shape of the Eq. (6) kernel: targets per thread (1, 2 or
  * 4) and the number of source chunks each target's sum is split into (1-64,
- * the same for every event, at most the event's tile count of 256 sources).  0 for either means "choose automatically" (the
- * default).  The split changes the FP32 summation order; the targets per
- * thread change the workgroups' origins and so the rounding of the pair
- * differences.  Applies to the current load and later ones; synchronises the
- * stream.  GCCD_E_INVALID outside those ranges. */
+ * the same for every event, at most the event's tile count of 256 sources).
+ * 0 for either means "choose automatically" (the default): one target per
+ * thread, and per event a chunk count near the one that gives about 64
+ * workgroups per compute unit, picked so that the event's tiles split into
+ * chunks as nearly equal as possible.  With one target per thread in the
+ * default precision, source tiles farther than the targets' box half-diagonal
+ * are summed in the expanded-square form (see gccd_set_precision).  The
+ * split changes the FP32 summation order; the targets per thread change the
+ * workgroups' origins and so the rounding of the pair differences.  Applies
+ * to the current load and later ones; synchronises the stream.
+ * GCCD_E_INVALID outside those ranges. */
 int gccd_set_launch(gccd_ctx* c, int32_t targets_per_thread, int32_t source_chunks);
 
 /* Picks the launch shape of gccd_set_launch by measurement: times the
  * Eq. (6) launch of the loaded state (its travelling holes against their
  * sources) for targets per thread 1, 2, 4 and source chunks 0 (automatic),
- * 4, 8, 16, 24, 32, 48, 64 (capped per event at its tile count), the median
- * of three launches each after one untimed, and keeps the fastest for this
- * load and later ones, as gccd_set_launch would.  About 100 launches: call
+ * 4, 8, 12, 16, 20, 24, 28, 32, 36, 40, 48, 56, 64 (capped per event at its
+ * tile count), the median of three launches each after one untimed, and
+ * keeps the fastest for this load and later ones, as gccd_set_launch would.
+ * About 170 launches: call
  * it once per workload.  The shape changes the FP32 summation order, so
  * results are reproducible across processes only for a fixed shape: the
  * chosen values (any pointer may be NULL) can be passed to gccd_set_launch.
@@ -199,8 +206,13 @@ int gccd_autotune(gccd_ctx* c, int32_t* targets_per_thread, int32_t* source_chun
  * per-tile sums in FP32; they differ in the origin the coordinates are
  * rounded relative to and in how the difference of a pair is formed.
  *   DEFAULT   origin at the centre of each workgroup's targets; pairs closer
- *             than a quarter of the targets' half-diagonal recomputed from
- *             the residuals of the coordinates (the fast, bounded mode)
+ *             than a quarter of the targets' half-diagonal rho recomputed
+ *             from the residuals of the coordinates (the fast, bounded
+ *             mode).  With one target per thread, source tiles whose box is
+ *             farther than rho from the targets' box take r^2 + eps^2 as
+ *             (|s|^2 + eps^2) + |t|^2 - 2 t.s and the sum as t sum w - sum s w
+ *             (one VALU operation fewer per pair; at most about 5e-6
+ *             relative error per term there)
  *   BLOCK     the same origins, no close-pair recomputation
  *   EVENT     one origin per event (the centre of its sources' bounding
  *             box), no recomputation

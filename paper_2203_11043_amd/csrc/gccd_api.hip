@@ -61,6 +61,8 @@ struct gccd_ctx {
     std::vector<uint32_t> tile_h;  // [E+1] first source tile of each event
     std::vector<int32_t> chunks_h; // [E] chunks of each event's field sum
     std::vector<int32_t> groups_h; // [E] partial-sum groups (2x chunks in the FP64 mode)
+    std::vector<int32_t> tail_h;   // [E] chunks of the tail layer (0: one layer)
+    std::vector<uint32_t> split_h; // [E] first tile of the tail layer
     std::vector<uint32_t> order_h; // events by decreasing size (work-item order)
     uint32_t n_tiles = 0;
     int max_chunks = 1;
@@ -225,12 +227,82 @@ uint32_t bits_for(uint64_t count) {  // smallest b with 2^b >= count (0 for coun
 // sources per chunk, and at least one tile per chunk (a small cloud is
 // latency-bound: it gains from every extra workgroup).  The FP64 mode stores
 // each chunk's sum in two groups and so takes at most kMaxChunks / 2 chunks.
+// An event's item length is set by its largest chunk, ceil(T/s) tiles of T;
+// the mean is T/s.  Near the chunk count s0 that fills the GPU, take the count
+// whose largest chunk is least above the mean (ties: the one nearest s0), so
+// that no few chunks carry one tile more than all the others.
+uint64_t balance_chunks(uint64_t tiles, uint64_t s0, uint64_t cap) {
+    if (tiles <= s0) return s0;
+    const uint64_t lo = std::max<uint64_t>(1, s0 * 9 / 10);
+    const uint64_t hi = std::min<uint64_t>(std::min<uint64_t>(cap, tiles), s0 * 5 / 4);
+    auto evenness = [tiles](uint64_t s) {
+        return (double)tiles / (double)(s * ((tiles + s - 1) / s));
+    };
+    uint64_t best = s0;
+    double best_e = evenness(s0);
+    for (uint64_t s = lo; s <= hi; ++s) {
+        const double e = evenness(s);
+        const uint64_t d = s > s0 ? s - s0 : s0 - s, bd = best > s0 ? best - s0 : s0 - best;
+        if (e > best_e + 1e-3 || (e > best_e - 1e-3 && d < bd)) {
+            best = s;
+            best_e = e;
+        }
+    }
+    return best;
+}
+
+// The tail layer.  Work items of equal length end raggedly: once the list
+// is dispatched, the compute units finish their last items over the span of
+// one item, with fewer and fewer workgroups resident.  In a launch of only a
+// few rounds of items that span is a sizeable share of the whole (measured:
+// a 1e5-hole cloud, 8-tile items, kept its slots 89 % busy).  So, with the
+// automatic choice, the largest events get a second layer: each of their last
+// T2 tiles is a chunk of its own, listed after every first-layer item, T2
+// chosen so that the tail work is about half a first-layer item per
+// workgroup slot.  The first T1 = T - T2 tiles keep the balanced round-robin
+// split.  The layers change which tiles share a partial sum, not the pairs
+// summed.
+void plan_tail(gccd_ctx* c, uint64_t cap) {
+    c->tail_h.assign(c->n_events, 0);
+    c->split_h.assign(c->n_events, 0);
+    if (c->chunks_fixed) return;
+    const uint64_t per = (uint64_t)kFieldThreads * (uint64_t)c->tpt;
+    const uint64_t slots =
+        (uint64_t)c->n_cu * (uint64_t)field_slots_per_cu(c->tpt, c->precision);
+    uint64_t items = 0, big = 0;
+    for (uint32_t e = 0; e < c->n_events; ++e) {
+        const uint64_t ne = c->off_h[e + 1] - c->off_h[e];
+        const uint64_t tiles = (ne + kTile - 1) / kTile, s = (uint64_t)c->chunks_h[e];
+        items += (ne + per - 1) / per * s;
+        big = std::max<uint64_t>(big, (tiles + s - 1) / s);
+    }
+    if (items >= 32 * slots || big < 4) return;  // many rounds, or items already short
+    int64_t need = (int64_t)(slots * big / 2);    // tile-units of tail work wanted
+    for (uint32_t e : c->order_h) {
+        if (need <= 0) break;
+        const uint64_t ne = c->off_h[e + 1] - c->off_h[e];
+        const uint64_t tiles = (ne + kTile - 1) / kTile, blocks = (ne + per - 1) / per;
+        const uint64_t s = (uint64_t)c->chunks_h[e];
+        if ((tiles + s - 1) / s < 4) break;  // smaller events have short items already
+        uint64_t t2 = std::min<uint64_t>(tiles / 4, ((uint64_t)need + blocks - 1) / blocks);
+        t2 = std::max<uint64_t>(t2, 1);
+        const uint64_t s2 = t2;  // one tile per tail chunk
+        if (s2 + 1 > cap) continue;
+        const uint64_t t1 = tiles - t2;
+        const uint64_t s1 = balance_chunks(t1, std::min<uint64_t>({s, cap - s2, t1}), cap - s2);
+        c->chunks_h[e] = (int32_t)(s1 + s2);
+        c->tail_h[e] = (int32_t)s2;
+        c->split_h[e] = (uint32_t)t1;
+        need -= (int64_t)(blocks * t2);
+    }
+}
+
 void choose_chunks(gccd_ctx* c) {
     uint64_t tblocks = 0;
     for (uint32_t e = 0; e < c->n_events; ++e)
         tblocks += (c->off_h[e + 1] - c->off_h[e] + kFieldThreads * c->tpt - 1) /
                    (kFieldThreads * c->tpt);
-    const uint64_t want = (uint64_t)c->n_cu * 48;
+    const uint64_t want = (uint64_t)c->n_cu * 64;
     c->chunks_h.assign(c->n_events, 1);
     c->groups_h.assign(c->n_events, 1);
     c->max_chunks = 1;
@@ -248,29 +320,47 @@ void choose_chunks(gccd_ctx* c) {
             s = std::max<uint64_t>((ne + 3071) / 3072, (want + tblocks - 1) / tblocks);
             s = std::min<uint64_t>(s, std::max<uint64_t>(1, tiles));
             s = std::max<uint64_t>(s, 1);
+            s = balance_chunks(tiles, std::min<uint64_t>(s, cap), cap);
         }
         s = std::min<uint64_t>(s, cap);
         c->chunks_h[e] = (int32_t)s;
-        c->groups_h[e] = (int32_t)(split ? 2 * s : s);
-        c->max_chunks = std::max(c->max_chunks, (int)s);
+    }
+    plan_tail(c, cap);
+    for (uint32_t e = 0; e < c->n_events; ++e) {
+        const int s = c->chunks_h[e];
+        c->groups_h[e] = split ? 2 * s : s;
+        c->max_chunks = std::max(c->max_chunks, s);
         c->max_groups = std::max(c->max_groups, c->groups_h[e]);
     }
 }
 
 // Work items for targets bound[e] of each event: largest events first, so the
-// longest workgroups start early.
+// longest workgroups start early.  Within a target block the chunks are
+// listed from chunk b mod S on: when S does not divide the tile count, the
+// first chunks carry one tile more, and the rotation keeps those longer
+// items from landing on the same compute units block after block (the
+// dispatcher deals workgroups to the XCDs and their CUs in launch order).
+// Only the launch order changes; each item's sums do not.
+// The tail layers of all events follow all first layers.
 int build_items(gccd_ctx* c, const uint32_t* bound) {
     const uint32_t per = (uint32_t)(kFieldThreads * c->tpt);
     size_t k = 0;
-    for (uint32_t e : c->order_h) {
-        const uint32_t blocks = (bound[e] + per - 1) / per;
-        const uint32_t s = (uint32_t)c->chunks_h[e];
-        for (uint32_t b = 0; b < blocks; ++b)
-            for (uint32_t ch = 0; ch < s; ++ch) {
-                if (k >= c->items_cap) return fail(c, GCCD_E_DEVICE, "work item overflow");
-                c->host_items[k++] = FieldItem{e, b, ch, s};
-            }
-    }
+    for (int layer = 0; layer < 2; ++layer)
+        for (uint32_t e : c->order_h) {
+            const uint32_t blocks = (bound[e] + per - 1) / per;
+            const uint32_t g = (uint32_t)c->chunks_h[e], s2 = (uint32_t)c->tail_h[e];
+            if (layer == 1 && s2 == 0) continue;
+            const uint32_t s = layer == 0 ? g - s2 : s2;       // chunks of this layer
+            const uint32_t g0 = layer == 0 ? 0u : g - s2;      // its first group
+            const uint32_t t0 = layer == 0 ? 0u : c->split_h[e];  // its first tile
+            const uint32_t end = (layer == 0 && s2) ? c->split_h[e] : kTilesToEnd;
+            for (uint32_t b = 0; b < blocks; ++b)
+                for (uint32_t j = 0; j < s; ++j) {
+                    if (k >= c->items_cap) return fail(c, GCCD_E_DEVICE, "work item overflow");
+                    const uint32_t q = (j + b) % s;
+                    c->host_items[k++] = FieldItem{e, b, g0 + q, g, t0 + q, end, s, 0};
+                }
+        }
     c->n_items = (uint32_t)k;
     if (k) {
         GCCD_HIP(c, hipMemcpyAsync(c->items_d, c->host_items, k * sizeof(FieldItem),
@@ -492,9 +582,9 @@ int build_near_items(gccd_ctx* c, uint32_t bound) {
     const uint32_t s = (uint32_t)c->near_chunks;
     size_t k = 0;
     for (uint32_t b = 0; b < blocks; ++b)
-        for (uint32_t ch = 0; ch < s; ++ch) {
+        for (uint32_t j = 0; j < s; ++j) {  // rotated as in build_items
             if (k >= c->items_cap) return fail(c, GCCD_E_DEVICE, "work item overflow");
-            c->host_items[k++] = FieldItem{0, b, ch, s};
+            c->host_items[k++] = FieldItem{0, b, (j + b) % s, s, (j + b) % s, kTilesToEnd, s, 0};
         }
     c->n_items = (uint32_t)k;
     if (k) {
@@ -924,10 +1014,10 @@ int gccd_autotune(gccd_ctx* c, int32_t* targets_per_thread, int32_t* source_chun
         GCCD_HIP(c, hipEventCreate(&e0));
         GCCD_HIP(c, hipEventCreate(&e1));
         static const int kT[3] = {1, 2, 4};
-        static const int kS[8] = {0, 4, 8, 16, 24, 32, 48, 64};
+        static const int kS[14] = {0, 4, 8, 12, 16, 20, 24, 28, 32, 36, 40, 48, 56, 64};
         int r = GCCD_OK;
         for (int ti = 0; ti < 3 && r == GCCD_OK; ++ti)
-            for (int si = 0; si < 8 && r == GCCD_OK; ++si) {
+            for (int si = 0; si < 14 && r == GCCD_OK; ++si) {
                 c->tpt_fixed = kT[ti];
                 c->chunks_fixed = kS[si];
                 c->tpt = kT[ti];

@@ -30,12 +30,21 @@ struct KeyLayout {
 
 // One workgroup of the Eq. (6) launch: targets [blk * 256 * TPT, ...) of the
 // event's target slots, against the source tiles chunk, chunk + nchunk, ...
+// One work item: target block blk of an event against the event's source
+// tiles first, first + step, first + 2 step, ... below min(end, the event's
+// current tile count), summed into partial-sum group `group` of the event's
+// `groups` (the FP64 mode writes its lo parts to group groups + group).
 struct FieldItem {
     uint32_t event;
     uint32_t blk;
-    uint32_t chunk;
-    uint32_t nchunk;
+    uint32_t group;
+    uint32_t groups;
+    uint32_t first;
+    uint32_t end;
+    uint32_t step;
+    uint32_t pad;
 };
+constexpr uint32_t kTilesToEnd = 0xFFFFFFFFu;  // FieldItem::end: up to the last tile
 
 struct FieldArgs {
     const FieldItem* items;
@@ -94,6 +103,7 @@ struct StepArgs {
 };
 
 // precision: a GCCD_PRECISION_* mode
+int field_slots_per_cu(int tpt, int precision);
 hipError_t launch_field(const FieldArgs& a, int tpt, int precision, uint32_t n_items,
                         hipStream_t s);
 hipError_t launch_step(const StepArgs& a, uint32_t n_slots, hipStream_t s);

@@ -279,15 +279,17 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles(FieldArgs a) {
     const uint32_t tbase = it.blk * (uint32_t)(kFieldThreads * TPT);
     if (tbase >= nt) return;  // the whole workgroup leaves before any barrier
 
-    // The item takes the event's source tiles chunk, chunk + S, chunk + 2S,
-    // ... of its T tiles.  Each tile is a compact region (the segment is
+    // The item takes the event's source tiles first, first + S, first + 2S,
+    // ... below its end.  Each tile is a compact region (the segment is
     // spatially sorted) whose bounding box is precomputed; dealing them
     // round-robin gives every chunk a sample of the whole cloud, so the
     // close pairs -- the costlier ones -- spread evenly over the workgroups.
     const uint32_t ntiles = (ns + kTile - 1) / kTile;
     const uint32_t tile0 = a.ev_tile[it.event];
-    const uint32_t chunk = it.chunk;
-    const uint32_t step_t = it.nchunk;
+    const uint32_t chunk = it.group;  // partial-sum group written
+    const uint32_t step_t = it.step;
+    const uint32_t t_first = it.first;
+    const uint32_t t_end = min(it.end, ntiles);
     const int tid = threadIdx.x;
 
     // targets and their bounding box
@@ -429,14 +431,14 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles(FieldArgs a) {
     };
 
     int buf = 0;
-    if (chunk < ntiles) {
-        fetch(chunk);
+    if (t_first < t_end) {
+        fetch(t_first);
         stage(0);
     }
     __syncthreads();
-    for (uint32_t t = chunk; t < ntiles; t += step_t) {
+    for (uint32_t t = t_first; t < t_end; t += step_t) {
         const uint32_t next = t + step_t;
-        if (next < ntiles) fetch(next);
+        if (next < t_end) fetch(next);
         const uint32_t cnt = min((uint32_t)kTile, ns - t * kTile);
 
         float bx[TPT], by[TPT], bz[TPT];
@@ -472,7 +474,7 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles(FieldArgs a) {
             ay[u] += by[u];
             az[u] += bz[u];
         }
-        if (next < ntiles) stage(buf ^ 1);
+        if (next < t_end) stage(buf ^ 1);
         __syncthreads();
         buf ^= 1;
     }
@@ -488,6 +490,286 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles(FieldArgs a) {
             outy[ts] = ay[t];
             outz[ts] = az[t];
         }
+    }
+}
+
+// Default precision, one target per lane: the far tiles in the expanded form.
+//
+// For a source tile whose bounding box lies more than rho from the targets'
+// box, every pair has |d| > rho, and the pair sum is taken from
+//     |d|^2 + eps^2 = (|s|^2 + eps^2) + |t|^2 - 2 t.s,
+//     sum d w = t sum w - sum s w,          w = (|d|^2 + eps^2)^{-3/2},
+// with s and t the hi parts relative to the workgroup origin.  The staged
+// tile holds -2 s and S = |s|^2 + eps^2 (rounded once from FP64), so a pair
+// costs an add, three FMAs for r^2, the reciprocal square root cubed and
+// four accumulations -- 11 VALU against 12 for the difference form.  The
+// expansion loses accuracy to cancellation: the partial results of r^2 are
+// bounded by (|s| + |t|)^2 <= (2 rho + |d|)^2 <= 9 |d|^2, so r^2 carries at
+// most 45u relative error and the term about 68u, plus the 8u of the dropped
+// lo parts (as for the difference form at |d| > rho): below 5e-6 in all.
+// The final t sum w - sum s w cancels by at most (|t| + |s|)/|d| <= 3, which
+// scales the FP32 summation error of those tiles by that factor.  It is
+// formed in FP64 from the FP32 sums.
+//
+// Tiles within rho of the targets' box take the difference form exactly as
+// field_tiles<1, DEFAULT> does (the sources' hi parts recovered from -2 s by
+// an exact halving inside the FMA), with the same rho/4 close-pair rule, so
+// the close pairs -- and whole small events, which have no far tiles -- are
+// summed bit for bit as by that kernel.
+template <bool CHECK>
+__device__ __forceinline__ void diff_pair(const float* __restrict__ lxp,
+                                          const float* __restrict__ lyp,
+                                          const float* __restrict__ lzp, uint32_t k, float m2x,
+                                          float m2y, float m2z, float thx, float thy, float thz,
+                                          float tlx, float tly, float tlz, float eps2, float rc2,
+                                          float& bx, float& by, float& bz) {
+    // thx + 0.5 (-2 s_x) rounds once, to the same value as thx - s_x
+    float dx = __builtin_fmaf(m2x, 0.5f, thx);
+    float dy = __builtin_fmaf(m2y, 0.5f, thy);
+    float dz = __builtin_fmaf(m2z, 0.5f, thz);
+    float r2 = __builtin_fmaf(dx, dx, eps2);
+    r2 = __builtin_fmaf(dy, dy, r2);
+    r2 = __builtin_fmaf(dz, dz, r2);
+    if (CHECK && __builtin_expect(__ballot(r2 < rc2) != 0ull, 0)) {
+        const float nlx = lxp[k], nly = lyp[k], nlz = lzp[k];
+        if (r2 < rc2) {
+            dx += tlx - nlx;
+            dy += tly - nly;
+            dz += tlz - nlz;
+            r2 = __builtin_fmaf(dx, dx, eps2);
+            r2 = __builtin_fmaf(dy, dy, r2);
+            r2 = __builtin_fmaf(dz, dz, r2);
+        }
+    }
+    const float inv = __builtin_amdgcn_rsqf(r2);
+    const float w = inv * inv * inv;
+    bx = __builtin_fmaf(dx, w, bx);
+    by = __builtin_fmaf(dy, w, by);
+    bz = __builtin_fmaf(dz, w, bz);
+}
+
+template <bool CHECK>
+__device__ __forceinline__ void diff_tile(const float* __restrict__ mxp,
+                                          const float* __restrict__ myp,
+                                          const float* __restrict__ mzp,
+                                          const float* __restrict__ lxp,
+                                          const float* __restrict__ lyp,
+                                          const float* __restrict__ lzp, uint32_t cnt, float thx,
+                                          float thy, float thz, float tlx, float tly, float tlz,
+                                          float eps2, float rc2, float& bx, float& by,
+                                          float& bz) {
+    uint32_t k = 0;
+    for (; k + 4 <= cnt; k += 4) {
+        const float4 x4 = *reinterpret_cast<const float4*>(mxp + k);
+        const float4 y4 = *reinterpret_cast<const float4*>(myp + k);
+        const float4 z4 = *reinterpret_cast<const float4*>(mzp + k);
+        diff_pair<CHECK>(lxp, lyp, lzp, k + 0, x4.x, y4.x, z4.x, thx, thy, thz, tlx, tly, tlz,
+                         eps2, rc2, bx, by, bz);
+        diff_pair<CHECK>(lxp, lyp, lzp, k + 1, x4.y, y4.y, z4.y, thx, thy, thz, tlx, tly, tlz,
+                         eps2, rc2, bx, by, bz);
+        diff_pair<CHECK>(lxp, lyp, lzp, k + 2, x4.z, y4.z, z4.z, thx, thy, thz, tlx, tly, tlz,
+                         eps2, rc2, bx, by, bz);
+        diff_pair<CHECK>(lxp, lyp, lzp, k + 3, x4.w, y4.w, z4.w, thx, thy, thz, tlx, tly, tlz,
+                         eps2, rc2, bx, by, bz);
+    }
+    for (; k < cnt; ++k)
+        diff_pair<CHECK>(lxp, lyp, lzp, k, mxp[k], myp[k], mzp[k], thx, thy, thz, tlx, tly, tlz,
+                         eps2, rc2, bx, by, bz);
+}
+
+__device__ __forceinline__ void expanded_pair(float m2x, float m2y, float m2z, float S, float T,
+                                              float thx, float thy, float thz, float& sw,
+                                              float& sx, float& sy, float& sz) {
+    float r2 = S + T;
+    r2 = __builtin_fmaf(thz, m2z, r2);
+    r2 = __builtin_fmaf(thy, m2y, r2);
+    r2 = __builtin_fmaf(thx, m2x, r2);
+    const float inv = __builtin_amdgcn_rsqf(r2);
+    const float w = inv * inv * inv;
+    sw += w;
+    sx = __builtin_fmaf(m2x, w, sx);
+    sy = __builtin_fmaf(m2y, w, sy);
+    sz = __builtin_fmaf(m2z, w, sz);
+}
+
+__global__ __launch_bounds__(kFieldThreads) void field_tiles_expanded(FieldArgs a) {
+    // staged planes: -2 s_x, -2 s_y, -2 s_z, |s|^2 + eps^2, lo_x, lo_y, lo_z
+    __shared__ __align__(16) float sh[2][7][kTile];
+    __shared__ double box[6][kFieldThreads / 64];
+    __shared__ double tbox[2][6];  // bounding box of the staged source tile
+
+    const FieldItem it = a.items[blockIdx.x];
+    const uint32_t off = a.ev_off[it.event];
+    const uint32_t ne = a.ev_off[it.event + 1] - off;
+    const uint32_t na = a.ev_active[it.event];
+    const uint32_t nt = a.targets_all ? ne : na;
+    const uint32_t ns = a.sources_all ? ne : na;
+    const uint32_t tbase = it.blk * (uint32_t)kFieldThreads;
+    if (tbase >= nt) return;  // the whole workgroup leaves before any barrier
+    const uint32_t ntiles = (ns + kTile - 1) / kTile;
+    const uint32_t tile0 = a.ev_tile[it.event];
+    const uint32_t chunk = it.group;  // partial-sum group written
+    const uint32_t step_t = it.step;
+    const uint32_t t_first = it.first;
+    const uint32_t t_end = min(it.end, ntiles);
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+
+    const uint32_t ts = tbase + (uint32_t)tid;
+    double px = 0.0, py = 0.0, pz = 0.0;
+    double lo_x = INFINITY, lo_y = INFINITY, lo_z = INFINITY;
+    double hi_x = -INFINITY, hi_y = -INFINITY, hi_z = -INFINITY;
+    if (ts < nt) {
+        px = a.px[off + ts];
+        py = a.py[off + ts];
+        pz = a.pz[off + ts];
+        lo_x = hi_x = px;
+        lo_y = hi_y = py;
+        lo_z = hi_z = pz;
+    }
+    lo_x = wave_min(lo_x);
+    lo_y = wave_min(lo_y);
+    lo_z = wave_min(lo_z);
+    hi_x = wave_max(hi_x);
+    hi_y = wave_max(hi_y);
+    hi_z = wave_max(hi_z);
+    if (lane == 0) {
+        box[0][wave] = lo_x;
+        box[1][wave] = lo_y;
+        box[2][wave] = lo_z;
+        box[3][wave] = hi_x;
+        box[4][wave] = hi_y;
+        box[5][wave] = hi_z;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < kFieldThreads / 64; ++w) {
+        lo_x = fmin(lo_x, box[0][w]);
+        lo_y = fmin(lo_y, box[1][w]);
+        lo_z = fmin(lo_z, box[2][w]);
+        hi_x = fmax(hi_x, box[3][w]);
+        hi_y = fmax(hi_y, box[4][w]);
+        hi_z = fmax(hi_z, box[5][w]);
+    }
+    lo_x = uniform(lo_x);
+    lo_y = uniform(lo_y);
+    lo_z = uniform(lo_z);
+    hi_x = uniform(hi_x);
+    hi_y = uniform(hi_y);
+    hi_z = uniform(hi_z);
+    const double ox = 0.5 * (lo_x + hi_x), oy = 0.5 * (lo_y + hi_y), oz = 0.5 * (lo_z + hi_z);
+    const double hx = 0.5 * (hi_x - lo_x), hy = 0.5 * (hi_y - lo_y), hz = 0.5 * (hi_z - lo_z);
+    const double rho2 = hx * hx + hy * hy + hz * hz;
+    const double rc2d = 0.0625 * rho2;  // (rho / 4)^2
+    const float rc2 = uniform((float)rc2d);
+    const double eps2d = (double)a.eps2;
+
+    float thx, thy, thz, tlx, tly, tlz, T;
+    {
+        // lanes past the last target sit at the origin (their sums are unused)
+        const double rx = (ts < nt ? px : ox) - ox, ry = (ts < nt ? py : oy) - oy,
+                     rz = (ts < nt ? pz : oz) - oz;
+        thx = (float)rx;
+        thy = (float)ry;
+        thz = (float)rz;
+        tlx = (float)(rx - (double)thx);
+        tly = (float)(ry - (double)thy);
+        tlz = (float)(rz - (double)thz);
+        T = (float)((double)thx * thx + (double)thy * thy + (double)thz * thz);
+    }
+    float sw = 0.0f, sx = 0.0f, sy = 0.0f, sz = 0.0f;  // far tiles
+    float ex = 0.0f, ey = 0.0f, ez = 0.0f;              // near tiles
+
+    double qx = 0.0, qy = 0.0, qz = 0.0;  // this lane's source of the next tile
+    double qb = 0.0;                      // lanes 0-5: one bound of that tile's box
+    auto fetch = [&](uint32_t t) {
+        const uint32_t i = t * kTile + (uint32_t)tid;
+        qx = ox;
+        qy = oy;
+        qz = oz;
+        if (i < ns) {
+            qx = a.px[off + i];
+            qy = a.py[off + i];
+            qz = a.pz[off + i];
+        }
+        if (tid < 6) qb = a.tile_box[(size_t)tid * a.tile_stride + tile0 + t];
+    };
+    auto stage = [&](int b) {
+        if (tid < 6) tbox[b][tid] = qb;
+        const double rx = qx - ox, ry = qy - oy, rz = qz - oz;
+        const float fx = (float)rx, fy = (float)ry, fz = (float)rz;
+        sh[b][0][tid] = -2.0f * fx;
+        sh[b][1][tid] = -2.0f * fy;
+        sh[b][2][tid] = -2.0f * fz;
+        sh[b][3][tid] = (float)((double)fx * fx + (double)fy * fy + (double)fz * fz + eps2d);
+        sh[b][4][tid] = (float)(rx - (double)fx);
+        sh[b][5][tid] = (float)(ry - (double)fy);
+        sh[b][6][tid] = (float)(rz - (double)fz);
+    };
+
+    int buf = 0;
+    if (t_first < t_end) {
+        fetch(t_first);
+        stage(0);
+    }
+    __syncthreads();
+    for (uint32_t t = t_first; t < t_end; t += step_t) {
+        const uint32_t next = t + step_t;
+        if (next < t_end) fetch(next);
+        const uint32_t cnt = min((uint32_t)kTile, ns - t * kTile);
+        const float* mxp = sh[buf][0];
+        const float* myp = sh[buf][1];
+        const float* mzp = sh[buf][2];
+        const double* tb = tbox[buf];
+        const double gx = fmax(0.0, fmax(tb[0] - hi_x, lo_x - tb[3]));
+        const double gy = fmax(0.0, fmax(tb[1] - hi_y, lo_y - tb[4]));
+        const double gz = fmax(0.0, fmax(tb[2] - hi_z, lo_z - tb[5]));
+        const double g2 = gx * gx + gy * gy + gz * gz;
+        if (g2 > rho2) {
+            const float* Sp = sh[buf][3];
+            float bw = 0.0f, bx = 0.0f, by = 0.0f, bz = 0.0f;
+            uint32_t k = 0;
+            for (; k + 4 <= cnt; k += 4) {
+                const float4 x4 = *reinterpret_cast<const float4*>(mxp + k);
+                const float4 y4 = *reinterpret_cast<const float4*>(myp + k);
+                const float4 z4 = *reinterpret_cast<const float4*>(mzp + k);
+                const float4 s4 = *reinterpret_cast<const float4*>(Sp + k);
+                expanded_pair(x4.x, y4.x, z4.x, s4.x, T, thx, thy, thz, bw, bx, by, bz);
+                expanded_pair(x4.y, y4.y, z4.y, s4.y, T, thx, thy, thz, bw, bx, by, bz);
+                expanded_pair(x4.z, y4.z, z4.z, s4.z, T, thx, thy, thz, bw, bx, by, bz);
+                expanded_pair(x4.w, y4.w, z4.w, s4.w, T, thx, thy, thz, bw, bx, by, bz);
+            }
+            for (; k < cnt; ++k)
+                expanded_pair(mxp[k], myp[k], mzp[k], Sp[k], T, thx, thy, thz, bw, bx, by, bz);
+            sw += bw;
+            sx += bx;
+            sy += by;
+            sz += bz;
+        } else {
+            float bx = 0.0f, by = 0.0f, bz = 0.0f;
+            if (g2 >= rc2d)
+                diff_tile<false>(mxp, myp, mzp, sh[buf][4], sh[buf][5], sh[buf][6], cnt, thx,
+                                 thy, thz, tlx, tly, tlz, a.eps2, rc2, bx, by, bz);
+            else
+                diff_tile<true>(mxp, myp, mzp, sh[buf][4], sh[buf][5], sh[buf][6], cnt, thx,
+                                thy, thz, tlx, tly, tlz, a.eps2, rc2, bx, by, bz);
+            ex += bx;
+            ey += by;
+            ez += bz;
+        }
+        if (next < t_end) stage(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+
+    if (ts < nt) {
+        // t sum w - sum s w, the second held as -2 sum s w
+        const float fx = (float)((double)thx * sw + 0.5 * (double)sx) + ex;
+        const float fy = (float)((double)thy * sw + 0.5 * (double)sy) + ey;
+        const float fz = (float)((double)thz * sw + 0.5 * (double)sz) + ez;
+        a.part[(size_t)(chunk * 3 + 0) * a.pstride + off + ts] = fx;
+        a.part[(size_t)(chunk * 3 + 1) * a.pstride + off + ts] = fy;
+        a.part[(size_t)(chunk * 3 + 2) * a.pstride + off + ts] = fz;
     }
 }
 
@@ -509,8 +791,10 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles_f64(FieldArgs a) {
     const uint32_t tbase = it.blk * (uint32_t)(kFieldThreads * TPT);
     if (tbase >= nt) return;
     const uint32_t ntiles = (ns + kTile - 1) / kTile;
-    const uint32_t chunk = it.chunk;
-    const uint32_t step_t = it.nchunk;
+    const uint32_t chunk = it.group;  // partial-sum group written
+    const uint32_t step_t = it.step;
+    const uint32_t t_first = it.first;
+    const uint32_t t_end = min(it.end, ntiles);
     const int tid = threadIdx.x;
     const double eps2 = a.eps2d;
 
@@ -544,14 +828,14 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles_f64(FieldArgs a) {
     };
 
     int buf = 0;
-    if (chunk < ntiles) {
-        fetch(chunk);
+    if (t_first < t_end) {
+        fetch(t_first);
         stage(0);
     }
     __syncthreads();
-    for (uint32_t t = chunk; t < ntiles; t += step_t) {
+    for (uint32_t t = t_first; t < t_end; t += step_t) {
         const uint32_t next = t + step_t;
-        if (next < ntiles) fetch(next);
+        if (next < t_end) fetch(next);
         const uint32_t cnt = min((uint32_t)kTile, ns - t * kTile);
         for (uint32_t k = 0; k < cnt; ++k) {
             const double sx = sh[buf][0][k], sy = sh[buf][1][k], sz = sh[buf][2][k];
@@ -567,7 +851,7 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles_f64(FieldArgs a) {
                 az[u] = fma(dz, w, az[u]);
             }
         }
-        if (next < ntiles) stage(buf ^ 1);
+        if (next < t_end) stage(buf ^ 1);
         __syncthreads();
         buf ^= 1;
     }
@@ -582,7 +866,7 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles_f64(FieldArgs a) {
             const float hi = (float)v[d];
             const float lo = (float)(v[d] - (double)hi);
             a.part[(size_t)(chunk * 3 + d) * a.pstride + off + ts] = hi;
-            a.part[(size_t)((step_t + chunk) * 3 + d) * a.pstride + off + ts] = lo;
+            a.part[(size_t)((it.groups + chunk) * 3 + d) * a.pstride + off + ts] = lo;
         }
     }
 }
@@ -592,7 +876,7 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles_f64(FieldArgs a) {
 // sources closer than a only (r^2 + eps^2 < a^2 + eps^2).  Work items,
 // origins, hi/lo staging and the close-pair recomputation are those of
 // field_tiles; the difference is which tiles are visited.  The item's
-// candidate tiles (chunk, chunk + S, ...) are tested 256 at a time against
+// candidate tiles (first, first + S, ...) are tested 256 at a time against
 // the targets' box, the ones within a are compacted into an LDS list, and
 // only those are staged and summed.  A tile entirely within a of every
 // target skips the per-pair cutoff.
@@ -614,8 +898,10 @@ __global__ __launch_bounds__(kFieldThreads) void near_tiles(FieldArgs a, const G
     if (tbase >= nt) return;
     const uint32_t ntiles = (ns + kTile - 1) / kTile;
     const uint32_t tile0 = a.ev_tile[it.event];
-    const uint32_t chunk = it.chunk;
-    const uint32_t step_t = it.nchunk;
+    const uint32_t chunk = it.group;  // partial-sum group written
+    const uint32_t step_t = it.step;
+    const uint32_t t_first = it.first;
+    const uint32_t t_end = min(it.end, ntiles);
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
 
@@ -708,14 +994,14 @@ __global__ __launch_bounds__(kFieldThreads) void near_tiles(FieldArgs a, const G
         sh[b][5][tid] = (float)(rz - (double)fz);
     };
 
-    const uint32_t ncand = chunk < ntiles ? (ntiles - chunk + step_t - 1) / step_t : 0u;
+    const uint32_t ncand = t_first < t_end ? (t_end - t_first + step_t - 1) / step_t : 0u;
     for (uint32_t base = 0; base < ncand; base += kFieldThreads) {
         // 1. which of the next 256 candidate tiles come within a of the targets
         const uint32_t m = base + (uint32_t)tid;
         bool keep = false;
         uint32_t t = 0;
         if (m < ncand) {
-            t = chunk + m * step_t;
+            t = t_first + m * step_t;
             const size_t g = (size_t)tile0 + t;
             const double* tb = a.tile_box;
             const size_t st = a.tile_stride;
@@ -830,11 +1116,53 @@ static hipError_t launch_field_prec(const FieldArgs& a, int tpt, uint32_t n_item
     return hipGetLastError();
 }
 
+// Workgroups of the Eq. (6) kernel that one compute unit holds at once for
+// this shape (registers and LDS permitting); 1 if the runtime cannot say.
+int field_slots_per_cu(int tpt, int precision) {
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+    if (precision == GCCD_PRECISION_FP64) {
+        if (tpt == 1)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &n, reinterpret_cast<const void*>(field_tiles_f64<1>), kFieldThreads, 0);
+        else if (tpt == 2)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &n, reinterpret_cast<const void*>(field_tiles_f64<2>), kFieldThreads, 0);
+        else
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &n, reinterpret_cast<const void*>(field_tiles_f64<4>), kFieldThreads, 0);
+    } else if (tpt == 1 && precision == GCCD_PRECISION_DEFAULT) {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &n, reinterpret_cast<const void*>(field_tiles_expanded), kFieldThreads, 0);
+    } else if (tpt == 1) {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &n, reinterpret_cast<const void*>(field_tiles<1, GCCD_PRECISION_BLOCK>),
+            kFieldThreads, 0);
+    } else if (tpt == 2) {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &n, reinterpret_cast<const void*>(field_tiles<2, GCCD_PRECISION_DEFAULT>),
+            kFieldThreads, 0);
+    } else {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &n, reinterpret_cast<const void*>(field_tiles<4, GCCD_PRECISION_DEFAULT>),
+            kFieldThreads, 0);
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return n > 0 ? n : 1;
+}
+
 hipError_t launch_field(const FieldArgs& a, int tpt, int precision, uint32_t n_items,
                         hipStream_t s) {
     if (n_items == 0) return hipSuccess;
     switch (precision) {
         case GCCD_PRECISION_DEFAULT:
+            if (tpt == 1) {
+                field_tiles_expanded<<<n_items, kFieldThreads, 0, s>>>(a);
+                return hipGetLastError();
+            }
             return launch_field_prec<GCCD_PRECISION_DEFAULT>(a, tpt, n_items, s);
         case GCCD_PRECISION_BLOCK:
             return launch_field_prec<GCCD_PRECISION_BLOCK>(a, tpt, n_items, s);
