@@ -244,6 +244,8 @@ def main() -> int:
                          "measuring the candidates first (gccd_autotune)")
     ap.add_argument("--no-closure", action="store_true",
                     help="skip the closure-versus-exact leg on the 1e6-hole cloud")
+    ap.add_argument("--schedule", choices=("grid", "queue", "graph"), default="grid",
+                    help="how gccd_run issues the steps (gccd_set_schedule)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (counter scale)")
     args = ap.parse_args()
@@ -304,6 +306,7 @@ def main() -> int:
     params = gccd.Params.from_device(w.device)
     ctx = gccd.gccd_init(params)
     gccd.gccd_set_launch(ctx, args.tpt, args.chunks)
+    gccd.gccd_set_schedule(ctx, args.schedule)
     xs = [torch.as_tensor(v).cuda() for v in (w.x, w.y, w.z)]
     tuned = None
     if args.workload == "batch":
@@ -345,6 +348,24 @@ def main() -> int:
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     s1 = gccd.gccd_stats(ctx)
+    # The timed steps above record HIP events around every field launch,
+    # which makes gccd_run issue them one by one.  The same number of steps
+    # again without the events shows what the graph schedule gives.
+    graph_pass = None
+    if args.schedule == "graph":
+        gccd.gccd_set_timing(ctx, False)
+        torch.cuda.synchronize()
+        g0 = gccd.gccd_stats(ctx)
+        t2 = time.perf_counter()
+        gdone = run(args.steps)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        g1 = gccd.gccd_stats(ctx)
+        graph_pass = {"steps": gdone, "ms_per_step": (t3 - t2) / max(gdone, 1) * 1e3,
+                      "pair_interactions_per_s":
+                          (g1["pair_interactions"] - g0["pair_interactions"]) / (t3 - t2),
+                      "graph_replays": g1["graph_replays"] - g0["graph_replays"],
+                      "graph_usable": g1["graph_usable"]}
     gccd.gccd_destroy(ctx)
     if done != args.steps:
         print(f"bench.py: only {done} of {args.steps} steps had travelling holes", file=sys.stderr)
@@ -395,6 +416,10 @@ def main() -> int:
             "targets_per_thread": s1["targets_per_thread"],
             "source_chunks": s1["source_chunks"],
             "max_source_chunks": s1["max_source_chunks"],
+            "schedule": (args.schedule + ": the timed steps are issued one by one (per-launch "
+                         "HIP events), see graph_pass for the replayed graphs"
+                         if args.schedule == "graph" else args.schedule),
+            "graph_pass": graph_pass,
             "launch_shape": ("autotuned: targets per thread %d, source chunks %s (%.2f ms)"
                              % (tuned[0], tuned[1] or "automatic", tuned[2])) if tuned else
                             ("fixed" if (args.tpt or args.chunks) else "automatic"),

@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define GCCD_ABI_VERSION 2u
+#define GCCD_ABI_VERSION 3u
 
 enum {
     GCCD_OK = 0,
@@ -86,6 +86,9 @@ typedef struct {
     int64_t max_source_chunks; /* largest source split over all events               */
     int64_t closure_steps;     /* steps whose Coulomb field came from the closure     */
     int64_t near_chunks;       /* source chunks of the closure's near sum (last run)  */
+    int64_t graph_replays;     /* 32-step HIP graphs replayed by gccd_run (schedule GRAPH) */
+    int32_t schedule;          /* the GCCD_SCHEDULE_* in force                        */
+    int32_t graph_usable;      /* 0 once a capture for this load was refused          */
 } gccd_stats_t;
 
 /* Creates a context bound to the current HIP device and to hip_stream (a
@@ -236,6 +239,37 @@ enum {
  * larger gccd_set_launch value is clamped).  Applies to the current load and
  * later ones; synchronises the stream.  GCCD_E_INVALID for an unknown mode. */
 int gccd_set_precision(gccd_ctx* c, int32_t mode);
+
+/* How gccd_run issues the time steps of the exact path (Coulomb on, no
+ * closure), the batched-events row of the work: thousands of events of
+ * uneven size in one launch per step, over a list of work items (event,
+ * target block, source chunk) ordered by cost, largest first.
+ *   GRID   one workgroup per work item; each launch is sized to the items
+ *   QUEUE  a persistent launch: as many workgroups as the GPU holds at once,
+ *          each taking the next work item from a counter in device memory
+ *          until the list is exhausted
+ *   GRAPH  the QUEUE launch, and each run of 32 consecutive steps (the
+ *          stretch between two reads of the counts by the host) captured
+ *          once as a HIP graph and replayed; the work items are rebuilt in
+ *          place between replays, so one capture serves the whole run
+ * QUEUE and GRAPH apply to one target per thread in the default precision;
+ * other shapes use GRID.  A capture that fails, or that would hold a
+ * memory-set node (the radix sort of a large load issues them), is dropped:
+ * that load's steps are then issued one by one.  Every schedule runs the
+ * same kernels on the same items, so results are bit-identical.  Per-launch
+ * timing (gccd_set_timing) needs events around each field launch, which
+ * graph replays do not provide: with timing on, GRAPH issues its steps one
+ * by one as QUEUE does.  Default: GRID, the fastest measured on MI355X (the
+ * hardware dispatcher already starts the items in list order as slots free
+ * up; the queue costs a reset launch and an atomic per item, and replaying
+ * the graph saves no device time at any size measured).  Synchronises the
+ * stream.  GCCD_E_INVALID for an unknown mode. */
+enum {
+    GCCD_SCHEDULE_GRID = 0,
+    GCCD_SCHEDULE_QUEUE = 1,
+    GCCD_SCHEDULE_GRAPH = 2
+};
+int gccd_set_schedule(gccd_ctx* c, int32_t mode);
 
 /* Far-field closure.  The Eq. (6) sum is split at a distance a: sources
  * closer than a are summed exactly, pair by pair, as in the exact path; the

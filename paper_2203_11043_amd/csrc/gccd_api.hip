@@ -39,6 +39,13 @@ enum : int {
     kMetaPending = 12,
     kMetaWords = 16
 };
+// words of the schedule buffer (device, and a pinned host copy to upload from)
+enum : int {
+    kSchedQueue = 0,  // persistent launch: next work item
+    kSchedItems = 1,  // persistent launch: work items in the list
+    kSchedStep = 2,   // list mode: step index of the first step of the current stretch
+    kSchedWords = 4
+};
 
 }  // namespace
 
@@ -117,6 +124,18 @@ struct gccd_ctx {
     int32_t closure_groups = 1;        // host copy of the closure's group count
     int64_t closure_steps = 0;
 
+    // how gccd_run issues the steps (GCCD_SCHEDULE_*), and the captured graph
+    int schedule = GCCD_SCHEDULE_GRID;
+    uint32_t* sched = nullptr;       // [kSchedWords]
+    uint32_t* host_sched = nullptr;  // pinned [kSchedWords]
+    int queue_slots = 0;             // workgroups of the persistent launch per CU (0: not yet asked)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    hipStream_t cap_stream = nullptr; // captures are recorded here (the context's stream
+                                      // may be the null stream, which cannot capture)
+    bool graph_refused = false;      // a capture for this load failed or held a memset node
+    int64_t graph_replays = 0;
+
     bool timing = false;
     std::vector<hipEvent_t> ev;
     int ev_used = 0;
@@ -176,7 +195,18 @@ void hfree(T*& ptr) {
     ptr = nullptr;
 }
 
+// The captured steps refer to the load's buffers and launch shape: any change
+// of those drops the graph (the next gccd_run captures again).
+void drop_graph(gccd_ctx* c) {
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+}
+
 void free_buffers(gccd_ctx* c) {
+    drop_graph(c);
+    c->graph_refused = false;
     dfree(c->x);
     dfree(c->y);
     dfree(c->z);
@@ -366,11 +396,17 @@ int build_items(gccd_ctx* c, const uint32_t* bound) {
         GCCD_HIP(c, hipMemcpyAsync(c->items_d, c->host_items, k * sizeof(FieldItem),
                                    hipMemcpyHostToDevice, c->stream));
     }
+    // the persistent launch reads the count on the device (the host copy is
+    // not written again before the stream has been synchronised)
+    c->host_sched[kSchedItems] = (uint32_t)k;
+    GCCD_HIP(c, hipMemcpyAsync(c->sched + kSchedItems, c->host_sched + kSchedItems,
+                               sizeof(uint32_t), hipMemcpyHostToDevice, c->stream));
     return GCCD_OK;
 }
 
 // Partial-sum buffer and work-item capacity for the current chunk choice.
 int size_chunk_buffers(gccd_ctx* c) {
+    drop_graph(c);
     dfree(c->part);
     dfree(c->items_d);
     hfree(c->host_items);
@@ -398,6 +434,7 @@ int size_chunk_buffers(gccd_ctx* c) {
 
 int ensure_part(gccd_ctx* c) {
     if (c->part_groups >= c->max_groups) return GCCD_OK;
+    drop_graph(c);
     dfree(c->part);
     if (hipMalloc(&c->part, (size_t)c->max_groups * 3 * (size_t)c->n * sizeof(float)) !=
         hipSuccess)
@@ -457,7 +494,21 @@ FieldArgs field_args(const gccd_ctx* c, bool targets_all) {
     fa.eps2d = c->p.softening_um * c->p.softening_um;
     fa.part = c->part;
     fa.pstride = (uint32_t)c->n;
+    fa.n_items = c->sched + kSchedItems;
+    fa.queue = c->sched + kSchedQueue;
     return fa;
+}
+
+// Workgroups of the persistent launch, or 0 for one workgroup per item.
+uint32_t queue_grid(gccd_ctx* c) {
+    if (c->schedule == GCCD_SCHEDULE_GRID || c->tpt != 1 ||
+        c->precision != GCCD_PRECISION_DEFAULT)
+        return 0;
+    if (c->queue_slots == 0) c->queue_slots = field_queue_slots_per_cu();
+    // no more workgroups than the load can ever have items (fixed per load,
+    // so a captured graph stays valid as the items shrink)
+    const size_t slots = (size_t)c->n_cu * (size_t)c->queue_slots;
+    return (uint32_t)std::max<size_t>(1, std::min(slots, c->items_cap));
 }
 
 // The sorted list from keys already written to keys[cur ^ 1]: sort into
@@ -560,6 +611,7 @@ void choose_near_chunks(gccd_ctx* c) {
 int ensure_closure_capacity(gccd_ctx* c) {
     const int groups = c->near_chunks + 1;
     if (groups > c->part_groups) {
+        drop_graph(c);  // the captured steps name the old buffers
         dfree(c->part);
         if (hipMalloc(&c->part, (size_t)groups * 3 * (size_t)c->n * sizeof(float)) != hipSuccess)
             return fail(c, GCCD_E_NOMEM, "closure partial-sum allocation failed");
@@ -567,6 +619,7 @@ int ensure_closure_capacity(gccd_ctx* c) {
     }
     const size_t items = (((size_t)c->n + kFieldThreads - 1) / kFieldThreads) * c->near_chunks;
     if (items > c->items_cap) {
+        drop_graph(c);
         dfree(c->items_d);
         hfree(c->host_items);
         if (hipMalloc(&c->items_d, items * sizeof(FieldItem)) != hipSuccess ||
@@ -687,6 +740,57 @@ int closure_field(gccd_ctx* c, bool targets_all, uint32_t nt, bool with_net) {
 
 }  // namespace
 
+namespace {
+
+// Captures kPoll steps issued by `issue` (step offsets 0 .. kPoll-1) as a
+// graph, recorded on a stream of the context's own and replayed later on the
+// caller's stream.  A capture that fails, or that holds a memory-set node
+// (replays of such nodes are not trusted here), is dropped and the load
+// marked: its steps are then issued one by one.  Nothing runs while
+// capturing.
+template <typename Issue>
+int capture_steps(gccd_ctx* c, Issue& issue) {
+    drop_graph(c);
+    if (!c->cap_stream) GCCD_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    c->ev_used = 0;
+    hipStream_t user = c->stream;
+    c->stream = c->cap_stream;
+    int r = GCCD_OK;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        for (uint32_t i = 0; i < (uint32_t)kPoll && r == GCCD_OK; ++i) r = issue(i, 0u);
+        e = hipStreamEndCapture(c->stream, &g);
+    }
+    c->stream = user;
+    c->ev_used = 0;
+    bool ok = r == GCCD_OK && e == hipSuccess && g != nullptr;
+    if (ok) {
+        size_t nn = 0;
+        ok = hipGraphGetNodes(g, nullptr, &nn) == hipSuccess;
+        std::vector<hipGraphNode_t> nodes(nn);
+        if (ok && nn) ok = hipGraphGetNodes(g, nodes.data(), &nn) == hipSuccess;
+        for (size_t i = 0; ok && i < nn; ++i) {
+            hipGraphNodeType t;
+            ok = hipGraphNodeGetType(nodes[i], &t) == hipSuccess && t != hipGraphNodeTypeMemset;
+        }
+    }
+    if (ok) ok = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0) == hipSuccess;
+    if (!ok) {
+        if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+        c->graph_exec = nullptr;
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        c->err.clear();
+        c->graph_refused = true;
+        return GCCD_OK;
+    }
+    c->graph = g;
+    return GCCD_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* gccd_strerror(int status) {
@@ -736,10 +840,24 @@ int gccd_init(const gccd_params* p, void* hip_stream, gccd_ctx** out) {
     c->vt = kKB * T / kQ;
 
     if (hipMalloc(&c->meta, kMetaWords * sizeof(uint32_t)) != hipSuccess ||
-        hipHostMalloc((void**)&c->host_meta, kMetaWords * sizeof(uint32_t)) != hipSuccess) {
+        hipHostMalloc((void**)&c->host_meta, kMetaWords * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&c->sched, kSchedWords * sizeof(uint32_t)) != hipSuccess ||
+        hipHostMalloc((void**)&c->host_sched, kSchedWords * sizeof(uint32_t)) != hipSuccess) {
         (void)hipFree(c->meta);
+        (void)hipHostFree(c->host_meta);
+        (void)hipFree(c->sched);
         delete c;
         return GCCD_E_NOMEM;
+    }
+    memset(c->host_sched, 0, kSchedWords * sizeof(uint32_t));
+    if (hipMemcpy(c->sched, c->host_sched, kSchedWords * sizeof(uint32_t),
+                  hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(c->meta);
+        (void)hipHostFree(c->host_meta);
+        (void)hipFree(c->sched);
+        (void)hipHostFree(c->host_sched);
+        delete c;
+        return GCCD_E_DEVICE;
     }
     *out = c;
     return GCCD_OK;
@@ -752,6 +870,9 @@ void gccd_destroy(gccd_ctx* c) {
     free_closure(c);
     (void)hipFree(c->meta);
     (void)hipHostFree(c->host_meta);
+    (void)hipFree(c->sched);
+    (void)hipHostFree(c->host_sched);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     delete c;
 }
@@ -915,6 +1036,17 @@ int gccd_set_precision(gccd_ctx* c, int32_t mode) {
     return GCCD_OK;
 }
 
+int gccd_set_schedule(gccd_ctx* c, int32_t mode) {
+    if (!c) return GCCD_E_INVALID;
+    if (mode < GCCD_SCHEDULE_GRID || mode > GCCD_SCHEDULE_GRAPH)
+        return fail(c, GCCD_E_INVALID, "gccd_set_schedule: unknown mode");
+    GCCD_HIP(c, hipStreamSynchronize(c->stream));
+    drop_graph(c);
+    c->graph_refused = false;
+    c->schedule = mode;
+    return GCCD_OK;
+}
+
 int gccd_set_closure(gccd_ctx* c, const float* weights, int64_t n_weights,
                      int64_t min_carriers) {
     if (!c) return GCCD_E_INVALID;
@@ -1029,7 +1161,7 @@ int gccd_autotune(gccd_ctx* c, int32_t* targets_per_thread, int32_t* source_chun
                 float t[3];
                 for (int rep = 0; rep < 4 && r == GCCD_OK; ++rep) {  // one untimed, three timed
                     if (hipEventRecord(e0, c->stream) != hipSuccess ||
-                        launch_field(fa, c->tpt, c->precision, c->n_items, c->stream) !=
+                        launch_field(fa, c->tpt, c->precision, c->n_items, queue_grid(c), c->stream) !=
                             hipSuccess ||
                         hipEventRecord(e1, c->stream) != hipSuccess ||
                         hipEventSynchronize(e1) != hipSuccess)
@@ -1140,34 +1272,66 @@ int gccd_run(gccd_ctx* c, double dt_ps, int64_t max_steps, int64_t* steps_done,
     sa.stats = reinterpret_cast<unsigned long long*>(c->meta + kMetaStats);
     sa.misc = reinterpret_cast<int32_t*>(c->meta + kMetaFlag);
 
+    // One time step: in list mode step i of the current stretch (its index is
+    // the base in sched[kSchedStep] plus i), else absolute step s.
+    if (c->list_mode) sa.step_base = c->sched + kSchedStep;
+    auto issue = [&](uint32_t i, uint32_t s) -> int {
+        if (c->list_mode) {
+            sa.step = i;
+            hipEvent_t* evp = nullptr;
+            int r = record_field_start(c, &evp);
+            if (r != GCCD_OK) return r;
+            if (use_closure) {
+                r = closure_field(c, false, (uint32_t)bound, true);
+                if (r != GCCD_OK) return r;
+            } else {
+                FieldArgs fa = field_args(c, false);
+                GCCD_HIP(c, launch_field(fa, c->tpt, c->precision, c->n_items, queue_grid(c),
+                                         c->stream));
+            }
+            if (evp) GCCD_HIP(c, hipEventRecord(evp[1], c->stream));
+            sa.keys_in = c->keys[c->cur];
+            sa.keys_out = c->keys[c->cur ^ 1];
+            GCCD_HIP(c, launch_step(sa, n, c->stream));
+            return finish_list(c);  // next step's sorted list, counts, positions
+        }
+        sa.step = s;
+        sa.cnt_in = c->meta + kMetaCount + (s % 3u);
+        sa.cnt_out = c->meta + kMetaCount + ((s + 1u) % 3u);
+        sa.cnt_clear = c->meta + kMetaCount + ((s + 2u) % 3u);
+        GCCD_HIP(c, launch_step(sa, n, c->stream));
+        return GCCD_OK;
+    };
+    // per-launch timing events cannot be read back from graph replays here:
+    // with timing on, the steps are issued one by one
+    const bool graphable = c->list_mode && !use_closure && !c->timing &&
+                           c->schedule == GCCD_SCHEDULE_GRAPH && queue_grid(c) > 0;
+
     int64_t k = 0;
     while (k < max_steps && bound > 0) {
         const int64_t chunk_steps = (max_steps - k < kPoll) ? (max_steps - k) : kPoll;
-        for (int64_t i = 0; i < chunk_steps; ++i) {
-            const uint32_t s = (uint32_t)(step0 + k + i);
-            sa.step = s;
-            if (c->list_mode) {
-                hipEvent_t* evp = nullptr;
-                int r = record_field_start(c, &evp);
+        if (c->list_mode) {
+            // the host copy is free: the stream was synchronised at the last poll
+            c->host_sched[kSchedStep] = (uint32_t)(step0 + k);
+            GCCD_HIP(c, hipMemcpyAsync(c->sched + kSchedStep, c->host_sched + kSchedStep,
+                                       sizeof(uint32_t), hipMemcpyHostToDevice, c->stream));
+        }
+        bool replayed = false;
+        if (graphable && chunk_steps == kPoll && !c->graph_refused) {
+            if (!c->graph_exec) {
+                int r = capture_steps(c, issue);
                 if (r != GCCD_OK) return r;
-                if (use_closure) {
-                    r = closure_field(c, false, (uint32_t)bound, true);
-                    if (r != GCCD_OK) return r;
-                } else {
-                    FieldArgs fa = field_args(c, false);
-                    GCCD_HIP(c, launch_field(fa, c->tpt, c->precision, c->n_items, c->stream));
-                }
-                if (evp) GCCD_HIP(c, hipEventRecord(evp[1], c->stream));
-                sa.keys_in = c->keys[c->cur];
-                sa.keys_out = c->keys[c->cur ^ 1];
-                GCCD_HIP(c, launch_step(sa, n, c->stream));
-                r = finish_list(c);  // next step's sorted list, counts, positions
+            }
+            if (c->graph_exec) {
+                GCCD_HIP(c, hipGraphLaunch(c->graph_exec, c->stream));
+                ++c->graph_replays;
+                replayed = true;
+            }
+        }
+        if (!replayed) {
+            for (int64_t i = 0; i < chunk_steps; ++i) {
+                int r = issue((uint32_t)i, (uint32_t)(step0 + k + i));
                 if (r != GCCD_OK) return r;
-            } else {
-                sa.cnt_in = c->meta + kMetaCount + (s % 3u);
-                sa.cnt_out = c->meta + kMetaCount + ((s + 1u) % 3u);
-                sa.cnt_clear = c->meta + kMetaCount + ((s + 2u) % 3u);
-                GCCD_HIP(c, launch_step(sa, n, c->stream));
             }
         }
         k += chunk_steps;
@@ -1233,7 +1397,7 @@ int gccd_field(gccd_ctx* c, double* ex, double* ey, double* ez) {
         r = build_items(c, all.data());
         if (r != GCCD_OK) return r;
         FieldArgs fa = field_args(c, true);
-        GCCD_HIP(c, launch_field(fa, c->tpt, c->precision, c->n_items, c->stream));
+        GCCD_HIP(c, launch_field(fa, c->tpt, c->precision, c->n_items, queue_grid(c), c->stream));
     }
     GCCD_HIP(c, launch_field_finish(c->part, n, c->ev_chunks_d, 0, 0, c->keys[c->cur],
                                     c->ev_off_d, c->kl, n, c->K, ex, ey, ez, c->stream));
@@ -1287,6 +1451,9 @@ int gccd_stats(gccd_ctx* c, gccd_stats_t* out) {
     out->source_chunks = c->loaded ? c->chunks_h[0] : 0;
     out->field_ms = c->field_ms;
     out->field_launches = c->field_launches;
+    out->graph_replays = c->graph_replays;
+    out->schedule = c->schedule;
+    out->graph_usable = c->graph_refused ? 0 : 1;
     if (!c->loaded) return GCCD_OK;
     GCCD_HIP(c, hipMemcpyAsync(c->host_meta, c->meta, kMetaWords * sizeof(uint32_t),
                                hipMemcpyDeviceToHost, c->stream));

@@ -63,6 +63,8 @@ struct FieldArgs {
     float* part;                // [group][3][pstride] FP32 partial sums by slot; the FP64
                                 // mode writes chunk c's sum as hi in group c, lo in c + S
     uint32_t pstride;
+    const uint32_t* n_items;    // persistent launch: the item count, in device memory
+    uint32_t* queue;            // persistent launch: [0] next item (zero before the launch)
 };
 
 // Everything the per-carrier update of one step needs.
@@ -91,7 +93,9 @@ struct StepArgs {
     double mu0, ec, beta, inv_beta;   // Eq. (2) at the context's T
     double dt_s;              // time step, s
     double vt;                // k_B T / q, V
-    uint32_t step;
+    uint32_t step;             // the step index, or its offset from *step_base
+    const uint32_t* step_base; // list mode: device word added to step (a graph replays
+                               // the same arguments at a new base)
     uint32_t event0;          // Philox event word of event 0
     uint32_t key0, key1;
     const uint32_t* cnt_in;   // carrier mode: travelling holes at the start of the step
@@ -104,7 +108,11 @@ struct StepArgs {
 
 // precision: a GCCD_PRECISION_* mode
 int field_slots_per_cu(int tpt, int precision);
+int field_queue_slots_per_cu();
+// queue_grid > 0: the persistent launch of that many workgroups (one target
+// per thread, default precision), after clearing the counter a.queue[0]
 hipError_t launch_field(const FieldArgs& a, int tpt, int precision, uint32_t n_items,
+                        uint32_t queue_grid,
                         hipStream_t s);
 hipError_t launch_step(const StepArgs& a, uint32_t n_slots, hipStream_t s);
 hipError_t launch_load(double* z, int32_t* cstep, const uint32_t* ev_off, uint32_t* ev_of,

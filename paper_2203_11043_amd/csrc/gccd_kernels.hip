@@ -592,13 +592,20 @@ __device__ __forceinline__ void expanded_pair(float m2x, float m2y, float m2z, f
     sz = __builtin_fmaf(m2z, w, sz);
 }
 
-__global__ __launch_bounds__(kFieldThreads) void field_tiles_expanded(FieldArgs a) {
-    // staged planes: -2 s_x, -2 s_y, -2 s_z, |s|^2 + eps^2, lo_x, lo_y, lo_z
-    __shared__ __align__(16) float sh[2][7][kTile];
-    __shared__ double box[6][kFieldThreads / 64];
-    __shared__ double tbox[2][6];  // bounding box of the staged source tile
+// One work item.  Every lane of the workgroup calls it with the same item;
+// it returns early only for an item without targets, before any barrier, and
+// otherwise ends after a barrier, so the LDS can take the next item at once.
+struct ExpandedLds {
+    float sh[2][7][kTile];  // staged: -2 s_x, -2 s_y, -2 s_z, |s|^2 + eps^2, lo_x, lo_y, lo_z
+    double box[6][kFieldThreads / 64];
+    double tbox[2][6];      // bounding box of the staged source tile
+};
 
-    const FieldItem it = a.items[blockIdx.x];
+__device__ __forceinline__ void expanded_item(const FieldArgs& a, const FieldItem it,
+                                              ExpandedLds& L) {
+    auto& sh = L.sh;
+    auto& box = L.box;
+    auto& tbox = L.tbox;
     const uint32_t off = a.ev_off[it.event];
     const uint32_t ne = a.ev_off[it.event + 1] - off;
     const uint32_t na = a.ev_active[it.event];
@@ -770,6 +777,32 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles_expanded(FieldArgs 
         a.part[(size_t)(chunk * 3 + 0) * a.pstride + off + ts] = fx;
         a.part[(size_t)(chunk * 3 + 1) * a.pstride + off + ts] = fy;
         a.part[(size_t)(chunk * 3 + 2) * a.pstride + off + ts] = fz;
+    }
+}
+
+// One workgroup per work item.
+__global__ __launch_bounds__(kFieldThreads) void field_tiles_expanded(FieldArgs a) {
+    __shared__ __align__(16) ExpandedLds L;
+    expanded_item(a, a.items[blockIdx.x], L);
+}
+
+// Persistent form: a fixed grid of workgroups takes the items in list order
+// from a counter (queue[0], zero before the launch) until *n_items are taken.
+// Every workgroup leaves once the counter has passed the end, so the grid
+// drains whatever the item count; the grid and the arguments stay the same
+// when the items are rebuilt, which lets a captured graph be replayed.
+__global__ __launch_bounds__(kFieldThreads) __attribute__((amdgpu_waves_per_eu(7)))
+void field_queue_expanded(FieldArgs a) {
+    __shared__ __align__(16) ExpandedLds L;
+    __shared__ uint32_t next;
+    const uint32_t n_items = *a.n_items;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(a.queue, 1u);
+        __syncthreads();
+        const uint32_t i = next;
+        __syncthreads();  // every lane has read `next` before lane 0 writes it again
+        if (i >= n_items) break;
+        expanded_item(a, a.items[i], L);
     }
 }
 
@@ -1118,6 +1151,17 @@ static hipError_t launch_field_prec(const FieldArgs& a, int tpt, uint32_t n_item
 
 // Workgroups of the Eq. (6) kernel that one compute unit holds at once for
 // this shape (registers and LDS permitting); 1 if the runtime cannot say.
+int field_queue_slots_per_cu() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &n, reinterpret_cast<const void*>(field_queue_expanded), kFieldThreads, 0) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return n > 0 ? n : 1;
+}
+
 int field_slots_per_cu(int tpt, int precision) {
     int n = 0;
     hipError_t e = hipErrorInvalidValue;
@@ -1155,7 +1199,14 @@ int field_slots_per_cu(int tpt, int precision) {
 }
 
 hipError_t launch_field(const FieldArgs& a, int tpt, int precision, uint32_t n_items,
-                        hipStream_t s) {
+                        uint32_t queue_grid, hipStream_t s) {
+    if (queue_grid > 0 && tpt == 1 && precision == GCCD_PRECISION_DEFAULT) {
+        // the item count is read on the device: launched even with none
+        const hipError_t e = launch_fill_u32(a.queue, 1u, 0u, s);
+        if (e != hipSuccess) return e;
+        field_queue_expanded<<<queue_grid, kFieldThreads, 0, s>>>(a);
+        return hipGetLastError();
+    }
     if (n_items == 0) return hipSuccess;
     switch (precision) {
         case GCCD_PRECISION_DEFAULT:
@@ -1359,6 +1410,7 @@ __device__ __forceinline__ double unit_open(uint32_t w) {
 //     atomic per wave.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kStepThreads) void step_update(StepArgs a) {
+    const uint32_t step = a.step + (a.step_base ? *a.step_base : 0u);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         unsigned long long holes, pairs = 0;
         if (a.list_mode) {
@@ -1371,7 +1423,7 @@ __global__ __launch_bounds__(kStepThreads) void step_update(StepArgs a) {
         if (holes > 0) {
             atomicAdd(&a.stats[0], holes);
             if (a.coulomb) atomicAdd(&a.stats[1], pairs);
-            a.misc[1] = (int32_t)(a.step + 1u);
+            a.misc[1] = (int32_t)(step + 1u);
         }
     }
     const int lane = threadIdx.x & 63;
@@ -1423,7 +1475,7 @@ __global__ __launch_bounds__(kStepThreads) void step_update(StepArgs a) {
                 double dy = mu * ey * a.dt_s * 1e4;
                 double dz = mu * ez * a.dt_s * 1e4;
                 if (a.diffusion) {
-                    uint32_t w0 = local, w1 = a.step, w2 = a.event0 + e, w3 = 0u;
+                    uint32_t w0 = local, w1 = step, w2 = a.event0 + e, w3 = 0u;
                     philox4x32_10(w0, w1, w2, w3, a.key0, a.key1);
                     const double r01 = sqrt(-2.0 * log(unit_open(w0)));
                     const double r23 = sqrt(-2.0 * log(unit_open(w2)));
@@ -1443,7 +1495,7 @@ __global__ __launch_bounds__(kStepThreads) void step_update(StepArgs a) {
                 a.z[j] = zn;
                 if (!isfinite(xn) || !isfinite(yn) || !isfinite(zn)) atomicOr(&a.misc[0], 1);
                 const bool collected = zn <= a.z_well;
-                if (collected) a.cstep[j] = (int32_t)(a.step + 1u);
+                if (collected) a.cstep[j] = (int32_t)(step + 1u);
                 keep = !collected;
                 if (a.list_mode) key = make_key(e, collected, xn, yn, zn, local, a.kl);
             }

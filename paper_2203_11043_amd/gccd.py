@@ -14,7 +14,7 @@ import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgccd.so")
-ABI_VERSION = 2
+ABI_VERSION = 3
 CLOSURE_WEIGHTS = 290784      # GCCD_CLOSURE_WEIGHTS
 
 GCCD_OK = 0
@@ -33,13 +33,14 @@ GCCD_PRECISION_COMPENSATED = 4
 GCCD_PRECISION_FP64 = 5
 PRECISION_MODES = {"default": 0, "block": 1, "event": 2, "absolute": 3, "compensated": 4,
                    "fp64": 5}
+SCHEDULES = {"grid": 0, "queue": 1, "graph": 2}   # GCCD_SCHEDULE_*
 
 # every symbol the header declares
 EXPORTS = ("gccd_init", "gccd_load", "gccd_load_events", "gccd_run", "gccd_image",
            "gccd_image_events", "gccd_field", "gccd_positions", "gccd_stats",
            "gccd_set_launch", "gccd_autotune", "gccd_set_precision", "gccd_set_closure",
-           "gccd_closure_parts", "gccd_set_timing", "gccd_strerror", "gccd_last_error",
-           "gccd_destroy")
+           "gccd_closure_parts", "gccd_set_timing", "gccd_set_schedule", "gccd_strerror",
+           "gccd_last_error", "gccd_destroy")
 
 
 class CParams(ctypes.Structure):
@@ -78,6 +79,9 @@ class CStats(ctypes.Structure):
         ("max_source_chunks", ctypes.c_int64),
         ("closure_steps", ctypes.c_int64),
         ("near_chunks", ctypes.c_int64),
+        ("graph_replays", ctypes.c_int64),
+        ("schedule", ctypes.c_int32),
+        ("graph_usable", ctypes.c_int32),
     ]
 
 
@@ -103,6 +107,7 @@ def _load():
     L.gccd_set_closure.argtypes = [P, P, i64, i64]
     L.gccd_closure_parts.argtypes = [P, P, P, P, P, P, P, P, P]
     L.gccd_set_timing.argtypes = [P, i32]
+    L.gccd_set_schedule.argtypes = [P, i32]
     L.gccd_strerror.argtypes = [ctypes.c_int]
     L.gccd_strerror.restype = ctypes.c_char_p
     L.gccd_last_error.argtypes = [P]
@@ -294,6 +299,12 @@ def gccd_autotune(ctx: int):
     t, s, ms = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_double(0.0)
     _check(ctx, lib.gccd_autotune(ctx, ctypes.byref(t), ctypes.byref(s), ctypes.byref(ms)))
     return t.value, s.value, ms.value
+
+
+def gccd_set_schedule(ctx: int, mode) -> None:
+    """mode: a GCCD_SCHEDULE_* value or its name ("grid", "queue", "graph")."""
+    m = SCHEDULES[mode] if isinstance(mode, str) else int(mode)
+    _check(ctx, lib.gccd_set_schedule(ctx, m))
 
 
 def gccd_set_precision(ctx: int, mode) -> None:

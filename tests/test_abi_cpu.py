@@ -29,7 +29,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported(g):
     names = declared_functions()
-    assert len(names) == 18
+    assert len(names) == 19
     for name in names:
         assert hasattr(g.lib, name), name
     assert sorted(g.EXPORTS) == names
@@ -44,9 +44,10 @@ def test_struct_layout_matches_header(g, tmp_path):
         'printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(gccd_params),'
         " offsetof(gccd_params, thickness_um), offsetof(gccd_params, coulomb),"
         " offsetof(gccd_params, seed), offsetof(gccd_params, event), sizeof(gccd_stats_t));\n"
-        'printf("%zu %zu %zu %zu %d\\n", offsetof(gccd_stats_t, field_ms),'
+        'printf("%zu %zu %zu %zu %zu %zu %d\\n", offsetof(gccd_stats_t, field_ms),'
         " offsetof(gccd_stats_t, source_chunks), offsetof(gccd_stats_t, max_source_chunks),"
-        " offsetof(gccd_stats_t, near_chunks), GCCD_CLOSURE_WEIGHTS);"
+        " offsetof(gccd_stats_t, near_chunks), offsetof(gccd_stats_t, graph_replays),"
+        " offsetof(gccd_stats_t, graph_usable), GCCD_CLOSURE_WEIGHTS);"
         "\nreturn 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o",
@@ -55,7 +56,8 @@ def test_struct_layout_matches_header(g, tmp_path):
     P, S = g.CParams, g.CStats
     want = [ctypes.sizeof(P), P.thickness_um.offset, P.coulomb.offset, P.seed.offset,
             P.event.offset, ctypes.sizeof(S), S.field_ms.offset, S.source_chunks.offset,
-            S.max_source_chunks.offset, S.near_chunks.offset, g.CLOSURE_WEIGHTS]
+            S.max_source_chunks.offset, S.near_chunks.offset, S.graph_replays.offset,
+            S.graph_usable.offset, g.CLOSURE_WEIGHTS]
     assert list(map(int, out)) == want
 
 
@@ -106,6 +108,7 @@ def test_null_arguments(g):
     assert L.gccd_set_launch(None, 0, 0) == g.GCCD_E_INVALID
     assert L.gccd_set_timing(None, 1) == g.GCCD_E_INVALID
     assert L.gccd_set_precision(None, 0) == g.GCCD_E_INVALID
+    assert L.gccd_set_schedule(None, 2) == g.GCCD_E_INVALID
     assert L.gccd_set_closure(None, None, 0, 0) == g.GCCD_E_INVALID
     assert L.gccd_autotune(None, None, None, None) == g.GCCD_E_INVALID
     assert L.gccd_closure_parts(None, None, None, None, None, None, None, None, None) == \
