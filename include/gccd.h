@@ -215,7 +215,10 @@ int gccd_autotune(gccd_ctx* c, int32_t* targets_per_thread, int32_t* source_chun
  *             farther than rho from the targets' box take r^2 + eps^2 as
  *             (|s|^2 + eps^2) + |t|^2 - 2 t.s and the sum as t sum w - sum s w
  *             (one VALU operation fewer per pair; at most about 5e-6
- *             relative error per term there)
+ *             relative error per term there); and in a load whose work
+ *             items fit in one round of workgroups (a small cloud), tiles
+ *             within rho/4 take the compensated difference in every pair
+ *             instead of the per-pair check
  *   BLOCK     the same origins, no close-pair recomputation
  *   EVENT     one origin per event (the centre of its sources' bounding
  *             box), no recomputation

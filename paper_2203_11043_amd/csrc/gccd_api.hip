@@ -129,6 +129,7 @@ struct gccd_ctx {
     uint32_t* sched = nullptr;       // [kSchedWords]
     uint32_t* host_sched = nullptr;  // pinned [kSchedWords]
     int queue_slots = 0;             // workgroups of the persistent launch per CU (0: not yet asked)
+    bool near_compensated = false;   // the load's items fit in one round of workgroup slots
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     hipStream_t cap_stream = nullptr; // captures are recorded here (the context's stream
@@ -416,6 +417,10 @@ int size_chunk_buffers(gccd_ctx* c) {
         items += (size_t)((ne + kFieldThreads - 1) / kFieldThreads) * (size_t)c->chunks_h[e];
     }
     c->items_cap = std::max<size_t>(items, 1);
+    // a load whose items fit in one round of workgroup slots is latency-bound:
+    // its close tiles take the branch-free compensated difference
+    c->near_compensated =
+        c->items_cap <= (size_t)c->n_cu * (size_t)field_slots_per_cu(1, GCCD_PRECISION_DEFAULT);
     c->groups_mode = 0;
     // the partial sums are only needed with repulsion on (a field call on a
     // load without it allocates them then: ensure_part)
@@ -496,6 +501,7 @@ FieldArgs field_args(const gccd_ctx* c, bool targets_all) {
     fa.pstride = (uint32_t)c->n;
     fa.n_items = c->sched + kSchedItems;
     fa.queue = c->sched + kSchedQueue;
+    fa.near_compensated = c->near_compensated ? 1 : 0;
     return fa;
 }
 

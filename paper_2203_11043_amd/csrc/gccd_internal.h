@@ -28,9 +28,9 @@ struct KeyLayout {
     uint32_t ebits;   // event bits
 };
 
-// One workgroup of the Eq. (6) launch: targets [blk * 256 * TPT, ...) of the
-// event's target slots, against the source tiles chunk, chunk + nchunk, ...
-// One work item: target block blk of an event against the event's source
+// One work item of the Eq. (6) launch (one workgroup, or one turn of a
+// persistent workgroup): targets [blk * 256 * TPT, ...) of the event's target
+// slots, that is target block blk of an event against the event's source
 // tiles first, first + step, first + 2 step, ... below min(end, the event's
 // current tile count), summed into partial-sum group `group` of the event's
 // `groups` (the FP64 mode writes its lo parts to group groups + group).
@@ -61,10 +61,12 @@ struct FieldArgs {
     float eps2;                 // softening length squared, um^2
     double eps2d;               // the same in FP64 (FP64 mode)
     float* part;                // [group][3][pstride] FP32 partial sums by slot; the FP64
-                                // mode writes chunk c's sum as hi in group c, lo in c + S
+                                // mode writes group g's sum as hi in group g, lo in G + g
     uint32_t pstride;
     const uint32_t* n_items;    // persistent launch: the item count, in device memory
     uint32_t* queue;            // persistent launch: [0] next item (zero before the launch)
+    int32_t near_compensated;   // one target per thread, default precision: tiles within
+                                // rho/4 take the compensated difference (small launches)
 };
 
 // Everything the per-carrier update of one step needs.

@@ -126,7 +126,8 @@ __device__ __forceinline__ double wave_max(double v) {
 //
 // One workgroup takes one work item: kFieldThreads*TPT consecutive target
 // slots of one event's spatially sorted segment (a compact region of the
-// cloud) and one chunk of that event's source tiles.  Sources are staged
+// cloud) and one chunk of that event's source tiles, dealt round-robin
+// (first, first + S, ... below the item's end).  Sources are staged
 // through LDS in tiles of kTile (double buffered: the next tile's global
 // loads are in flight while the current one is consumed); every lane of
 // every wave reads the same LDS words, so the reads are bank-conflict-free
@@ -548,6 +549,49 @@ __device__ __forceinline__ void diff_pair(const float* __restrict__ lxp,
     bz = __builtin_fmaf(dz, w, bz);
 }
 
+// Difference form with the lo parts in every pair (the compensated
+// difference of the COMPENSATED mode), branch-free.
+__device__ __forceinline__ void comp_pair(float m2x, float m2y, float m2z, float lx, float ly,
+                                          float lz, float thx, float thy, float thz, float tlx,
+                                          float tly, float tlz, float eps2, float& bx, float& by,
+                                          float& bz) {
+    const float dx = __builtin_fmaf(m2x, 0.5f, thx) + (tlx - lx);
+    const float dy = __builtin_fmaf(m2y, 0.5f, thy) + (tly - ly);
+    const float dz = __builtin_fmaf(m2z, 0.5f, thz) + (tlz - lz);
+    float r2 = __builtin_fmaf(dx, dx, eps2);
+    r2 = __builtin_fmaf(dy, dy, r2);
+    r2 = __builtin_fmaf(dz, dz, r2);
+    const float inv = __builtin_amdgcn_rsqf(r2);
+    const float w = inv * inv * inv;
+    bx = __builtin_fmaf(dx, w, bx);
+    by = __builtin_fmaf(dy, w, by);
+    bz = __builtin_fmaf(dz, w, bz);
+}
+
+__device__ __forceinline__ void comp_tile(const float* __restrict__ mxp, const float* __restrict__ myp,
+                                          const float* __restrict__ mzp, const float* __restrict__ lxp,
+                                          const float* __restrict__ lyp, const float* __restrict__ lzp,
+                                          uint32_t cnt, float thx, float thy, float thz, float tlx,
+                                          float tly, float tlz, float eps2, float& bx, float& by,
+                                          float& bz) {
+    uint32_t k = 0;
+    for (; k + 4 <= cnt; k += 4) {
+        const float4 x4 = *reinterpret_cast<const float4*>(mxp + k);
+        const float4 y4 = *reinterpret_cast<const float4*>(myp + k);
+        const float4 z4 = *reinterpret_cast<const float4*>(mzp + k);
+        const float4 a4 = *reinterpret_cast<const float4*>(lxp + k);
+        const float4 b4 = *reinterpret_cast<const float4*>(lyp + k);
+        const float4 c4 = *reinterpret_cast<const float4*>(lzp + k);
+        comp_pair(x4.x, y4.x, z4.x, a4.x, b4.x, c4.x, thx, thy, thz, tlx, tly, tlz, eps2, bx, by, bz);
+        comp_pair(x4.y, y4.y, z4.y, a4.y, b4.y, c4.y, thx, thy, thz, tlx, tly, tlz, eps2, bx, by, bz);
+        comp_pair(x4.z, y4.z, z4.z, a4.z, b4.z, c4.z, thx, thy, thz, tlx, tly, tlz, eps2, bx, by, bz);
+        comp_pair(x4.w, y4.w, z4.w, a4.w, b4.w, c4.w, thx, thy, thz, tlx, tly, tlz, eps2, bx, by, bz);
+    }
+    for (; k < cnt; ++k)
+        comp_pair(mxp[k], myp[k], mzp[k], lxp[k], lyp[k], lzp[k], thx, thy, thz, tlx, tly, tlz, eps2,
+                  bx, by, bz);
+}
+
 template <bool CHECK>
 __device__ __forceinline__ void diff_tile(const float* __restrict__ mxp,
                                           const float* __restrict__ myp,
@@ -601,6 +645,13 @@ struct ExpandedLds {
     double tbox[2][6];      // bounding box of the staged source tile
 };
 
+// COMP: tiles closer than rho/4 to the targets take the compensated
+// difference in every pair instead of the per-pair check and its branch.
+// In a launch of at most one round of workgroups (a small cloud) nearly
+// every wave finds a close pair in such tiles, the branch is taken almost
+// always, and the branch-free form halves the launch; in a full GPU the
+// check is cheaper per pair.
+template <bool COMP>
 __device__ __forceinline__ void expanded_item(const FieldArgs& a, const FieldItem it,
                                               ExpandedLds& L) {
     auto& sh = L.sh;
@@ -757,6 +808,9 @@ __device__ __forceinline__ void expanded_item(const FieldArgs& a, const FieldIte
             if (g2 >= rc2d)
                 diff_tile<false>(mxp, myp, mzp, sh[buf][4], sh[buf][5], sh[buf][6], cnt, thx,
                                  thy, thz, tlx, tly, tlz, a.eps2, rc2, bx, by, bz);
+            else if (COMP)
+                comp_tile(mxp, myp, mzp, sh[buf][4], sh[buf][5], sh[buf][6], cnt, thx, thy,
+                          thz, tlx, tly, tlz, a.eps2, bx, by, bz);
             else
                 diff_tile<true>(mxp, myp, mzp, sh[buf][4], sh[buf][5], sh[buf][6], cnt, thx,
                                 thy, thz, tlx, tly, tlz, a.eps2, rc2, bx, by, bz);
@@ -781,9 +835,10 @@ __device__ __forceinline__ void expanded_item(const FieldArgs& a, const FieldIte
 }
 
 // One workgroup per work item.
+template <bool COMP>
 __global__ __launch_bounds__(kFieldThreads) void field_tiles_expanded(FieldArgs a) {
     __shared__ __align__(16) ExpandedLds L;
-    expanded_item(a, a.items[blockIdx.x], L);
+    expanded_item<COMP>(a, a.items[blockIdx.x], L);
 }
 
 // Persistent form: a fixed grid of workgroups takes the items in list order
@@ -791,6 +846,7 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles_expanded(FieldArgs 
 // Every workgroup leaves once the counter has passed the end, so the grid
 // drains whatever the item count; the grid and the arguments stay the same
 // when the items are rebuilt, which lets a captured graph be replayed.
+template <bool COMP>
 __global__ __launch_bounds__(kFieldThreads) __attribute__((amdgpu_waves_per_eu(7)))
 void field_queue_expanded(FieldArgs a) {
     __shared__ __align__(16) ExpandedLds L;
@@ -802,15 +858,15 @@ void field_queue_expanded(FieldArgs a) {
         const uint32_t i = next;
         __syncthreads();  // every lane has read `next` before lane 0 writes it again
         if (i >= n_items) break;
-        expanded_item(a, a.items[i], L);
+        expanded_item<COMP>(a, a.items[i], L);
     }
 }
 
 // Eq. (6) entirely in FP64: the difference, r^2 + eps^2, r^-3 = 1/(q sqrt q)
 // with IEEE square root and division, and the sums.  Same work items, tiles
-// and source dealing as field_tiles; chunk c's FP64 sum is written as the
-// FP32 pair hi (group c) and lo (group c + S), which the FP64 reduction of
-// the groups adds back exactly.
+// and source dealing as field_tiles; the FP64 sum of group g is written as
+// the FP32 pair hi (group g) and lo (group G + g, G the event's groups),
+// which the FP64 reduction of the groups adds back exactly.
 template <int TPT>
 __global__ __launch_bounds__(kFieldThreads) void field_tiles_f64(FieldArgs a) {
     __shared__ double sh[2][3][kTile];
@@ -1154,7 +1210,7 @@ static hipError_t launch_field_prec(const FieldArgs& a, int tpt, uint32_t n_item
 int field_queue_slots_per_cu() {
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &n, reinterpret_cast<const void*>(field_queue_expanded), kFieldThreads, 0) !=
+            &n, reinterpret_cast<const void*>(field_queue_expanded<false>), kFieldThreads, 0) !=
         hipSuccess) {
         (void)hipGetLastError();
         return 1;
@@ -1177,7 +1233,7 @@ int field_slots_per_cu(int tpt, int precision) {
                 &n, reinterpret_cast<const void*>(field_tiles_f64<4>), kFieldThreads, 0);
     } else if (tpt == 1 && precision == GCCD_PRECISION_DEFAULT) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &n, reinterpret_cast<const void*>(field_tiles_expanded), kFieldThreads, 0);
+            &n, reinterpret_cast<const void*>(field_tiles_expanded<false>), kFieldThreads, 0);
     } else if (tpt == 1) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
             &n, reinterpret_cast<const void*>(field_tiles<1, GCCD_PRECISION_BLOCK>),
@@ -1204,14 +1260,20 @@ hipError_t launch_field(const FieldArgs& a, int tpt, int precision, uint32_t n_i
         // the item count is read on the device: launched even with none
         const hipError_t e = launch_fill_u32(a.queue, 1u, 0u, s);
         if (e != hipSuccess) return e;
-        field_queue_expanded<<<queue_grid, kFieldThreads, 0, s>>>(a);
+        if (a.near_compensated)
+            field_queue_expanded<true><<<queue_grid, kFieldThreads, 0, s>>>(a);
+        else
+            field_queue_expanded<false><<<queue_grid, kFieldThreads, 0, s>>>(a);
         return hipGetLastError();
     }
     if (n_items == 0) return hipSuccess;
     switch (precision) {
         case GCCD_PRECISION_DEFAULT:
             if (tpt == 1) {
-                field_tiles_expanded<<<n_items, kFieldThreads, 0, s>>>(a);
+                if (a.near_compensated)
+                    field_tiles_expanded<true><<<n_items, kFieldThreads, 0, s>>>(a);
+                else
+                    field_tiles_expanded<false><<<n_items, kFieldThreads, 0, s>>>(a);
                 return hipGetLastError();
             }
             return launch_field_prec<GCCD_PRECISION_DEFAULT>(a, tpt, n_items, s);
