@@ -524,7 +524,6 @@ int finish_list(gccd_ctx* c) {
     const uint32_t end_bit = c->kl.lbits + kCurveBits + 1 + c->kl.ebits;
     GCCD_HIP(c, sort_keys(c->sort_tmp, c->sort_tmp_bytes, c->keys[c->cur ^ 1], c->keys[c->cur], n,
                           end_bit, c->stream));
-    GCCD_HIP(c, launch_fill_u32(c->meta + kMetaPending, 4, 0u, c->stream));
     GCCD_HIP(c, launch_count(c->keys[c->cur], c->ev_off_d, c->n_events, c->kl,
                              c->p.collected_are_sources,
                              c->ev_active_d,

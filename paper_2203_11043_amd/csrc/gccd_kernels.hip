@@ -1327,9 +1327,16 @@ hipError_t launch_make_keys(const double* x, const double* y, const double* z,
     return hipGetLastError();
 }
 
-__global__ void count_active(const uint64_t* keys, const uint32_t* ev_off, uint32_t n_events,
-                             KeyLayout kl, int sources_all, uint32_t* ev_active,
-                             unsigned long long* pending) {
+// SINGLE: one workgroup of kCountThreads covers every event and writes the
+// totals itself (no clearing launch before it); otherwise the totals are
+// cleared beforehand and every thread adds its events' counts atomically.
+constexpr int kCountThreads = 256;
+
+template <bool SINGLE>
+__global__ __launch_bounds__(kCountThreads) void count_active(
+    const uint64_t* keys, const uint32_t* ev_off, uint32_t n_events, KeyLayout kl,
+    int sources_all, uint32_t* ev_active, unsigned long long* pending) {
+    unsigned long long holes = 0, pairs = 0;
     for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n_events;
          e += gridDim.x * blockDim.x) {
         const uint32_t off = ev_off[e], ne = ev_off[e + 1] - off;
@@ -1342,10 +1349,30 @@ __global__ void count_active(const uint64_t* keys, const uint32_t* ev_off, uint3
                 lo = mid + 1;
         }
         ev_active[e] = lo;
-        if (lo > 0) {
-            const unsigned long long src = sources_all ? ne : lo;
+        const unsigned long long src = sources_all ? ne : lo;
+        if (SINGLE) {
+            holes += lo;
+            pairs += (unsigned long long)lo * src;
+        } else if (lo > 0) {
             atomicAdd(&pending[0], (unsigned long long)lo);
             atomicAdd(&pending[1], (unsigned long long)lo * src);
+        }
+    }
+    if (SINGLE) {
+        __shared__ unsigned long long red[2][kCountThreads];
+        red[0][threadIdx.x] = holes;
+        red[1][threadIdx.x] = pairs;
+        __syncthreads();
+        for (int h = kCountThreads / 2; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) {
+                red[0][threadIdx.x] += red[0][threadIdx.x + h];
+                red[1][threadIdx.x] += red[1][threadIdx.x + h];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            pending[0] = red[0][0];
+            pending[1] = red[1][0];
         }
     }
 }
@@ -1353,8 +1380,15 @@ __global__ void count_active(const uint64_t* keys, const uint32_t* ev_off, uint3
 hipError_t launch_count(const uint64_t* keys, const uint32_t* ev_off, uint32_t n_events,
                         KeyLayout kl, int sources_all, uint32_t* ev_active,
                         unsigned long long* pending, hipStream_t s) {
-    count_active<<<grid_for(n_events, 256, 1024), 256, 0, s>>>(keys, ev_off, n_events, kl,
-                                                              sources_all, ev_active, pending);
+    if (n_events <= (uint32_t)kCountThreads) {
+        count_active<true><<<1, kCountThreads, 0, s>>>(keys, ev_off, n_events, kl, sources_all,
+                                                        ev_active, pending);
+        return hipGetLastError();
+    }
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(pending), 4, 0u, s);
+    if (e != hipSuccess) return e;
+    count_active<false><<<grid_for(n_events, kCountThreads, 1024), kCountThreads, 0, s>>>(
+        keys, ev_off, n_events, kl, sources_all, ev_active, pending);
     return hipGetLastError();
 }
 
