@@ -171,7 +171,7 @@ __device__ __forceinline__ void pair_terms(const float* __restrict__ lxp,
                                            const float (&thx)[TPT], const float (&thy)[TPT],
                                            const float (&thz)[TPT], const float (&tlx)[TPT],
                                            const float (&tly)[TPT], const float (&tlz)[TPT],
-                                           float eps2, float rc2, float (&ax)[TPT],
+                                           float eps2, const float (&rc2)[TPT], float (&ax)[TPT],
                                            float (&ay)[TPT], float (&az)[TPT],
                                            float cut2 = 0.0f) {
     float dx[TPT], dy[TPT], dz[TPT], r2[TPT];
@@ -189,7 +189,7 @@ __device__ __forceinline__ void pair_terms(const float* __restrict__ lxp,
         r2[t] = __builtin_fmaf(dx[t], dx[t], eps2);
         r2[t] = __builtin_fmaf(dy[t], dy[t], r2[t]);
         r2[t] = __builtin_fmaf(dz[t], dz[t], r2[t]);
-        if (DIFF == kDiffNear) near |= r2[t] < rc2;
+        if (DIFF == kDiffNear) near |= r2[t] < rc2[t];
     }
     if (DIFF == kDiffNear && __builtin_expect(__ballot(near) != 0ull, 0)) {
         // wave-uniform branch, taken only when some lane of the wave has a
@@ -197,7 +197,7 @@ __device__ __forceinline__ void pair_terms(const float* __restrict__ lxp,
         const float nlx = lxp[k], nly = lyp[k], nlz = lzp[k];
 #pragma unroll
         for (int t = 0; t < TPT; ++t) {
-            if (r2[t] < rc2) {
+            if (r2[t] < rc2[t]) {
                 dx[t] += tlx[t] - nlx;
                 dy[t] += tly[t] - nly;
                 dz[t] += tlz[t] - nlz;
@@ -231,7 +231,7 @@ __device__ __forceinline__ void tile_terms(const float* __restrict__ hxp,
                                            const float (&thx)[TPT], const float (&thy)[TPT],
                                            const float (&thz)[TPT], const float (&tlx)[TPT],
                                            const float (&tly)[TPT], const float (&tlz)[TPT],
-                                           float eps2, float rc2, float (&bx)[TPT],
+                                           float eps2, const float (&rc2)[TPT], float (&bx)[TPT],
                                            float (&by)[TPT], float (&bz)[TPT],
                                            float cut2 = 0.0f) {
     uint32_t k = 0;
@@ -387,9 +387,12 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles(FieldArgs a) {
     }
     const double hx = 0.5 * (hi_x - lo_x), hy = 0.5 * (hi_y - lo_y), hz = 0.5 * (hi_z - lo_z);
     const double rc2d = 0.0625 * (hx * hx + hy * hy + hz * hz);  // (rho / 4)^2
-    const float rc2 = uniform((float)rc2d);
 
-    float thx[TPT], thy[TPT], thz[TPT], tlx[TPT], tly[TPT], tlz[TPT];
+    // rc2[t]: the close-pair radius squared of target t, a quarter of its own
+    // distance from the origin (the error bound 4u (1 + |t - o| / |d|) holds
+    // for every target; a lane-wise radius takes the branch less often than
+    // the workgroup's rho / 4); 0 for slots past the last target
+    float thx[TPT], thy[TPT], thz[TPT], tlx[TPT], tly[TPT], tlz[TPT], rc2[TPT];
     float ax[TPT], ay[TPT], az[TPT];
 #pragma unroll
     for (int t = 0; t < TPT; ++t) {
@@ -400,6 +403,10 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles(FieldArgs a) {
         tlx[t] = (float)(rx - (double)thx[t]);
         tly[t] = (float)(ry - (double)thy[t]);
         tlz[t] = (float)(rz - (double)thz[t]);
+        const uint32_t ts = tbase + (uint32_t)(t * kFieldThreads + tid);
+        rc2[t] = ts < nt ? 0.0625f * (float)((double)thx[t] * thx[t] + (double)thy[t] * thy[t] +
+                                             (double)thz[t] * thz[t])
+                         : 0.0f;
         ax[t] = 0.0f;
         ay[t] = 0.0f;
         az[t] = 0.0f;
@@ -719,7 +726,6 @@ __device__ __forceinline__ void expanded_item(const FieldArgs& a, const FieldIte
     const double hx = 0.5 * (hi_x - lo_x), hy = 0.5 * (hi_y - lo_y), hz = 0.5 * (hi_z - lo_z);
     const double rho2 = hx * hx + hy * hy + hz * hz;
     const double rc2d = 0.0625 * rho2;  // (rho / 4)^2
-    const float rc2 = uniform((float)rc2d);
     const double eps2d = (double)a.eps2;
 
     float thx, thy, thz, tlx, tly, tlz, T;
@@ -735,6 +741,9 @@ __device__ __forceinline__ void expanded_item(const FieldArgs& a, const FieldIte
         tlz = (float)(rz - (double)thz);
         T = (float)((double)thx * thx + (double)thy * thy + (double)thz * thz);
     }
+    // this lane's close-pair radius squared: a quarter of its target's
+    // distance from the origin, as in field_tiles (0 for the padding lanes)
+    const float rc2 = 0.0625f * T;
     float sw = 0.0f, sx = 0.0f, sy = 0.0f, sz = 0.0f;  // far tiles
     float ex = 0.0f, ey = 0.0f, ez = 0.0f;              // near tiles
 
@@ -1042,11 +1051,10 @@ __global__ __launch_bounds__(kFieldThreads) void near_tiles(FieldArgs a, const G
     const double ox = 0.5 * (lo_x + hi_x), oy = 0.5 * (lo_y + hi_y), oz = 0.5 * (lo_z + hi_z);
     const double hx = 0.5 * (hi_x - lo_x), hy = 0.5 * (hi_y - lo_y), hz = 0.5 * (hi_z - lo_z);
     const double rc2d = 0.0625 * (hx * hx + hy * hy + hz * hz);
-    const float rc2 = uniform((float)rc2d);
     const double a2 = uniform(gp->a2);
     const float cut2 = uniform((float)gp->cut2);
 
-    float thx[1], thy[1], thz[1], tlx[1], tly[1], tlz[1], ax[1], ay[1], az[1];
+    float thx[1], thy[1], thz[1], tlx[1], tly[1], tlz[1], ax[1], ay[1], az[1], rc2[1];
     {
         const double rx = px - ox, ry = py - oy, rz = pz - oz;
         thx[0] = (float)rx;
@@ -1056,6 +1064,10 @@ __global__ __launch_bounds__(kFieldThreads) void near_tiles(FieldArgs a, const G
         tly[0] = (float)(ry - (double)thy[0]);
         tlz[0] = (float)(rz - (double)thz[0]);
         ax[0] = ay[0] = az[0] = 0.0f;
+        // close-pair radius of this target, as in field_tiles
+        rc2[0] = ts < nt ? 0.0625f * (float)((double)thx[0] * thx[0] + (double)thy[0] * thy[0] +
+                                             (double)thz[0] * thz[0])
+                         : 0.0f;
     }
 
     double qx = 0.0, qy = 0.0, qz = 0.0, qb = 0.0;
