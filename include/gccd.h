@@ -209,9 +209,10 @@ int gccd_autotune(gccd_ctx* c, int32_t* targets_per_thread, int32_t* source_chun
  * per-tile sums in FP32; they differ in the origin the coordinates are
  * rounded relative to and in how the difference of a pair is formed.
  *   DEFAULT   origin at the centre of each workgroup's targets; pairs closer
- *             than a quarter of the targets' half-diagonal rho recomputed
- *             from the residuals of the coordinates (the fast, bounded
- *             mode).  With one target per thread, source tiles whose box is
+ *             than a quarter of the target's distance from that origin
+ *             (at most a quarter of the targets' half-diagonal rho)
+ *             recomputed from the residuals of the coordinates (the fast,
+ *             bounded mode).  With one target per thread, source tiles whose box is
  *             farther than rho from the targets' box take r^2 + eps^2 as
  *             (|s|^2 + eps^2) + |t|^2 - 2 t.s and the sum as t sum w - sum s w
  *             (one VALU operation fewer per pair; at most about 5e-6

@@ -138,10 +138,12 @@ __device__ __forceinline__ double wave_max(double v) {
 // staged sources alike, as the FP32 pair hi = fl32(x - o), lo = fl32(x - o -
 // hi).  A pair difference d is first formed from the hi parts alone; its
 // error is at most 2u (rho + |d|), and since the Jacobian of d/|d|^3 has norm
-// 2/|d|^3 the term's relative error is at most 4u (1 + rho/|d|).  Pairs
-// closer than rho/4 -- rare, and found with one compare per pair, or ruled
-// out for a whole source tile by its bounding box -- are recomputed with the
-// lo parts added, which makes their difference accurate to about u |d|.
+// 2/|d|^3 the term's relative error is at most 4u (1 + |t - o|/|d|) <= 4u (1 +
+// rho/|d|).  Pairs closer than a quarter of the target's distance |t - o|
+// from the origin -- rare, found with one compare per pair, or ruled out for
+// a whole source tile whose bounding box is rho/4 or more from the targets'
+// box -- are recomputed with the lo parts added, which makes their
+// difference accurate to about u |d|.
 // Every term therefore carries at most 20u (1.2e-6) relative error from the
 // coordinates, plus about 8u from r^2, the hardware reciprocal square root
 // (cubed for r^-3) and the products, so each carrier's field is within about
