@@ -1538,6 +1538,7 @@ __global__ __launch_bounds__(kStepThreads) void step_update(StepArgs a) {
     }
     const int lane = threadIdx.x & 63;
     const double two_pi = 6.283185307179586476925286766559;
+    uint32_t kept = 0;  // carrier mode: this wave's holes still travelling (wave-uniform)
     for (uint32_t base = blockIdx.x * kStepThreads; base < a.n_all;
          base += gridDim.x * kStepThreads) {
         const uint32_t slot = base + threadIdx.x;
@@ -1611,10 +1612,18 @@ __global__ __launch_bounds__(kStepThreads) void step_update(StepArgs a) {
             }
             if (a.list_mode) a.keys_out[slot] = key;
         }
-        if (!a.list_mode) {
-            const unsigned long long m = __ballot(keep);
-            if (m && lane == __ffsll((long long)m) - 1)
-                atomicAdd(a.cnt_out, (uint32_t)__popcll(m));
+        if (!a.list_mode) kept += (uint32_t)__popcll(__ballot(keep));
+    }
+    if (!a.list_mode) {
+        // one atomic per workgroup: a counter taking one per wave and grid-
+        // stride turn (2.6e5 at 2^24 holes) serialised the whole step
+        __shared__ uint32_t wave_kept[kStepThreads / 64];
+        if (lane == 0) wave_kept[threadIdx.x >> 6] = kept;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t t = 0;
+            for (int w = 0; w < kStepThreads / 64; ++w) t += wave_kept[w];
+            if (t) atomicAdd(a.cnt_out, t);
         }
     }
 }
