@@ -1644,6 +1644,7 @@ __global__ __launch_bounds__(kStepThreads) void load_prepare(double* z, int32_t*
                                                              uint32_t n, double thickness,
                                                              double z_well, uint32_t* cnt) {
     const int lane = threadIdx.x & 63;
+    uint32_t kept = 0;  // this wave's travelling holes (wave-uniform)
     for (uint32_t base = blockIdx.x * kStepThreads; base < n; base += gridDim.x * kStepThreads) {
         const uint32_t j = base + threadIdx.x;
         bool keep = false;
@@ -1656,8 +1657,16 @@ __global__ __launch_bounds__(kStepThreads) void load_prepare(double* z, int32_t*
             keep = !collected;
             ev_of[j] = event_of(ev_off, n_events, j);
         }
-        const unsigned long long m = __ballot(keep);
-        if (m && lane == __ffsll((long long)m) - 1) atomicAdd(cnt, (uint32_t)__popcll(m));
+        kept += (uint32_t)__popcll(__ballot(keep));
+    }
+    // one atomic per workgroup, as in step_update
+    __shared__ uint32_t wave_kept[kStepThreads / 64];
+    if (lane == 0) wave_kept[threadIdx.x >> 6] = kept;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < kStepThreads / 64; ++w) t += wave_kept[w];
+        if (t) atomicAdd(cnt, t);
     }
 }
 
