@@ -1,4 +1,4 @@
-"""Judges the far-field closure against the exact path on the same GPU.
+"""Compares the far-field closure with the exact path on the same GPU.
 
     python -m paper_2203_11043_amd.closure_eval --out DIR [--n 1000000] [--seeds 2000]
 
