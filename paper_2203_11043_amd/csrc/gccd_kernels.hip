@@ -523,9 +523,12 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles(FieldArgs a) {
 //
 // Tiles within rho of the targets' box take the difference form exactly as
 // field_tiles<1, DEFAULT> does (the sources' hi parts recovered from -2 s by
-// an exact halving inside the FMA), with the same rho/4 close-pair rule, so
+// an exact halving inside the FMA), with the same close-pair rule (tiles
+// within rho/4 of the targets' box checked pair by pair against a quarter of
+// each target's distance from the origin), so in a launch that fills the GPU
 // the close pairs -- and whole small events, which have no far tiles -- are
-// summed bit for bit as by that kernel.
+// summed bit for bit as by that kernel.  Small loads differ on purpose: see
+// COMP below.
 template <bool CHECK>
 __device__ __forceinline__ void diff_pair(const float* __restrict__ lxp,
                                           const float* __restrict__ lyp,
