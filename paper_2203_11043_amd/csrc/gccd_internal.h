@@ -9,7 +9,9 @@ namespace gccd {
 constexpr int kFieldThreads = 256;   // threads per Eq. (6) workgroup (4 wave64)
 constexpr int kTile = 256;           // sources staged in LDS per tile
 constexpr int kMaxChunks = 64;       // largest source split of one target's sum
-constexpr int kBoxRows = 30;         // per source tile: its box, then its four quarters' boxes
+constexpr int kBoxRows = 126;        // per source tile: its box (rows 0-5), its four 64-slot
+                                     // quarters' boxes (row 6 + 4 k + q for bound k of quarter
+                                     // q), its sixteen 16-slot groups' boxes (row 30 + 16 k + g)
 constexpr int kStepThreads = 256;
 
 // Carrier lists hold one 64-bit key per carrier:

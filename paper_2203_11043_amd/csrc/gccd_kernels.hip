@@ -981,13 +981,15 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles_f64(FieldArgs a) {
 // field_tiles; the difference is which tiles are visited.  The item's
 // candidate tiles (first, first + S, ...) are tested 256 at a time against
 // the targets' box, the ones within a are compacted into an LDS list, and
-// only those are staged and summed.  A tile entirely within a of every
-// target skips the per-pair cutoff.
+// only those are staged and summed, each wave taking only the 16-source
+// groups of a staged tile that come within a of its own 64 targets.  A
+// group entirely within a of every target of the wave skips the per-pair
+// cutoff.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kFieldThreads) void near_tiles(FieldArgs a, const GridParams* gp) {
     __shared__ __align__(16) float sh[2][6][kTile];
     __shared__ double box[6][kFieldThreads / 64];
-    __shared__ double tbox[2][kBoxRows];  // the staged tile's box and its quarters' boxes
+    __shared__ double tbox[2][kBoxRows];  // the staged tile's boxes (tile, quarters, groups)
     __shared__ uint32_t list[kFieldThreads];
     __shared__ uint32_t wcount[kFieldThreads / 64];
 
@@ -1143,25 +1145,34 @@ __global__ __launch_bounds__(kFieldThreads) void near_tiles(FieldArgs a, const G
             const uint32_t cnt = min((uint32_t)kTile, ns - tt * kTile);
             float bx[1] = {0.0f}, by[1] = {0.0f}, bz[1] = {0.0f};
             const double* tb = tbox[buf];
-            // each wave takes the quarters of the tile within a of its own targets
-#pragma unroll
-            for (int qd = 0; qd < kTile / 64; ++qd) {
-                const uint32_t k0 = (uint32_t)qd * 64u;
-                if (k0 >= cnt) break;
-                const uint32_t kn = min(64u, cnt - k0);
-                const double* qb6 = tb + 6 + qd;  // bound k of this quarter at qb6[4 k]
-                const double gx = fmax(0.0, fmax(qb6[0] - wh_x, wl_x - qb6[12]));
-                const double gy = fmax(0.0, fmax(qb6[4] - wh_y, wl_y - qb6[16]));
-                const double gz = fmax(0.0, fmax(qb6[8] - wh_z, wl_z - qb6[20]));
+            // each wave takes the 16-source groups of the tile within a of its
+            // own targets: lane l tests group l % 16 (three ballots collect the
+            // answers), then the wave sums the groups that pass, one by one
+            uint32_t cand, in_m, far_m;
+            {
+                const int grp = lane & 15;
+                const double* gb = tb + 30 + grp;  // bound k of the group at gb[16 k]
+                const double gx = fmax(0.0, fmax(gb[0] - wh_x, wl_x - gb[48]));
+                const double gy = fmax(0.0, fmax(gb[16] - wh_y, wl_y - gb[64]));
+                const double gz = fmax(0.0, fmax(gb[32] - wh_z, wl_z - gb[80]));
                 const double gap2 = gx * gx + gy * gy + gz * gz;
-                if (!(gap2 < a2)) continue;
-                const bool far_q = gap2 >= rc2d;
                 // largest distance between the boxes: every pair well inside a
                 // (a margin far above the FP32 error of r^2) needs no per-pair test
-                const double mx = fmax(qb6[12] - wl_x, wh_x - qb6[0]);
-                const double my = fmax(qb6[16] - wl_y, wh_y - qb6[4]);
-                const double mz = fmax(qb6[20] - wl_z, wh_z - qb6[8]);
-                const bool inside = mx * mx + my * my + mz * mz < 0.9999 * a2;
+                const double mx = fmax(gb[48] - wl_x, wh_x - gb[0]);
+                const double my = fmax(gb[64] - wl_y, wh_y - gb[16]);
+                const double mz = fmax(gb[80] - wl_z, wh_z - gb[32]);
+                const bool valid = (uint32_t)grp * 16u < cnt;
+                cand = (uint32_t)__ballot(valid && gap2 < a2) & 0xFFFFu;
+                in_m = (uint32_t)__ballot(mx * mx + my * my + mz * mz < 0.9999 * a2) & 0xFFFFu;
+                far_m = (uint32_t)__ballot(gap2 >= rc2d) & 0xFFFFu;
+            }
+            while (cand) {
+                const int grp = __builtin_ctz(cand);
+                cand &= cand - 1u;
+                const uint32_t k0 = (uint32_t)grp * 16u;
+                const uint32_t kn = min(16u, cnt - k0);
+                const bool inside = (in_m >> grp) & 1u;
+                const bool far_q = (far_m >> grp) & 1u;
                 const float* hxp = sh[buf][0] + k0;
                 const float* hyp = sh[buf][1] + k0;
                 const float* hzp = sh[buf][2] + k0;
@@ -1413,7 +1424,9 @@ hipError_t launch_count(const uint64_t* keys, const uint32_t* ev_off, uint32_t n
 // t = g - ev_tile[e]): positions of every slot of the tile, bounding box of
 // the slots that are sources (rows 0-5 of box: low x, y, z, high x, y, z),
 // and the same for each 64-slot quarter of the tile (row 6 + 4 k + q for
-// bound k of quarter q), which the near-field kernel culls by.
+// bound k of quarter q) and each 16-slot group (row 30 + 16 k + g), which
+// the near-field kernel culls by.  The group boxes are the first four steps
+// of the lane reduction that gives the quarter boxes.
 __global__ __launch_bounds__(kTile) void gather_tiles(
     const uint64_t* keys, const uint32_t* ev_off, const uint32_t* ev_tile,
     const uint32_t* tile_event, const uint32_t* ev_active, int sources_all, KeyLayout kl,
@@ -1442,12 +1455,32 @@ __global__ __launch_bounds__(kTile) void gather_tiles(
             lz = hz = vz;
         }
     }
-    lx = wave_min(lx);
-    ly = wave_min(ly);
-    lz = wave_min(lz);
-    hx = wave_max(hx);
-    hy = wave_max(hy);
-    hz = wave_max(hz);
+    // butterfly over lanes: after the strides 1..8 every lane holds its
+    // 16-slot group's box, after 16 and 32 its quarter's
+#pragma unroll
+    for (int m = 1; m <= 8; m <<= 1) {
+        lx = fmin(lx, __shfl_xor(lx, m));
+        ly = fmin(ly, __shfl_xor(ly, m));
+        lz = fmin(lz, __shfl_xor(lz, m));
+        hx = fmax(hx, __shfl_xor(hx, m));
+        hy = fmax(hy, __shfl_xor(hy, m));
+        hz = fmax(hz, __shfl_xor(hz, m));
+    }
+    if ((threadIdx.x & 15) == 0) {
+        const int grp = threadIdx.x >> 4;  // 0 .. 15
+        const double v[6] = {lx, ly, lz, hx, hy, hz};
+#pragma unroll
+        for (int k = 0; k < 6; ++k) box[(size_t)(30 + 16 * k + grp) * stride + g] = v[k];
+    }
+#pragma unroll
+    for (int m = 16; m <= 32; m <<= 1) {
+        lx = fmin(lx, __shfl_xor(lx, m));
+        ly = fmin(ly, __shfl_xor(ly, m));
+        lz = fmin(lz, __shfl_xor(lz, m));
+        hx = fmax(hx, __shfl_xor(hx, m));
+        hy = fmax(hy, __shfl_xor(hy, m));
+        hz = fmax(hz, __shfl_xor(hz, m));
+    }
     const int wave = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
         red[0][wave] = lx;
