@@ -1601,10 +1601,27 @@ __global__ __launch_bounds__(kStepThreads) void step_update(StepArgs a) {
                 if (a.coulomb) {
                     double sx = 0.0, sy = 0.0, sz = 0.0;
                     const int nchunk = a.ev_chunks[e];
-                    for (int c = 0; c < nchunk; ++c) {
-                        sx += (double)a.part[(size_t)(c * 3 + 0) * a.pstride + slot];
-                        sy += (double)a.part[(size_t)(c * 3 + 1) * a.pstride + slot];
-                        sz += (double)a.part[(size_t)(c * 3 + 2) * a.pstride + slot];
+                    const float* pp = a.part + slot;
+                    const size_t ps = a.pstride;
+                    int c = 0;
+                    // four groups' loads in flight ahead of their adds (same order)
+                    for (; c + 4 <= nchunk; c += 4) {
+                        float v[4][3];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+#pragma unroll
+                            for (int d = 0; d < 3; ++d) v[u][d] = pp[(size_t)((c + u) * 3 + d) * ps];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            sx += (double)v[u][0];
+                            sy += (double)v[u][1];
+                            sz += (double)v[u][2];
+                        }
+                    }
+                    for (; c < nchunk; ++c) {
+                        sx += (double)pp[(size_t)(c * 3 + 0) * ps];
+                        sy += (double)pp[(size_t)(c * 3 + 1) * ps];
+                        sz += (double)pp[(size_t)(c * 3 + 2) * ps];
                     }
                     ecx = a.K * sx;
                     ecy = a.K * sy;
