@@ -151,6 +151,67 @@ def test_field_collected_not_sources(g, W, orc):
     assert ea <= FIELD_TOL
 
 
+def test_field_far_from_origin_across_key_wrap(g, W, orc):
+    """A cloud 60 mm from the coordinate origin, centred on a multiple of the
+    1024 um period of the sort key's cell index in x and y: its holes get keys
+    from both ends of the curve, and the pair offsets are formed relative to
+    each workgroup's origin, so the field must not depend on where it sits."""
+    n = 20000
+    cx, cy = 60 * 1024.0 + 0.3, 2 * 1024.0 - 0.2
+    x, y, z = W.gaussian_cloud(n, W.cloud_sigma(n), (cx, cy, 300.0), 41, stream=6)
+    assert np.any(x < 60 * 1024.0) and np.any(x > 60 * 1024.0)
+    p, d = dev_params(g, W)
+    E, st = gpu_field(g, p, x, y, z)
+    Eo, A = orc.field([x, y, z], with_magnitude=True)
+    ea, er = field_errors(E, Eo, A)
+    report(f"cloud n={n} at x={cx:.1f} um, y={cy:.1f} um", ea, er)
+    assert ea <= FIELD_TOL
+    # the same holes near the origin: the same field to rounding
+    E0, _ = gpu_field(g, p, x - cx + 480.0, y - cy + 480.0, z)
+    Eo0, A0 = orc.field([x - cx + 480.0, y - cy + 480.0, z], with_magnitude=True)
+    assert field_errors(E0, Eo0, A0)[0] <= FIELD_TOL
+    assert np.max(np.linalg.norm(E - E0, axis=0) / A) <= 2 * FIELD_TOL
+
+
+def test_field_coincident_holes(g, W, orc):
+    """Every position held by three holes: a coincident pair's softened term
+    is zero (Eq. (6) at r = 0), and the three copies feel the same field."""
+    u = 1700
+    x, y, z = W.gaussian_cloud(u, W.cloud_sigma(3 * u), (480.0, 480.0, 250.0), 43, stream=7)
+    x, y, z = np.tile(x, 3), np.tile(y, 3), np.tile(z, 3)
+    p, d = dev_params(g, W)
+    E, st = gpu_field(g, p, x, y, z)
+    Eo, A = orc.field([x, y, z], with_magnitude=True)
+    ea, er = field_errors(E, Eo, A)
+    report(f"cloud n={3 * u}, each position held by 3 holes", ea, er)
+    assert ea <= FIELD_TOL
+    for k in (1, 2):
+        assert np.max(np.linalg.norm(E[:, k * u:(k + 1) * u] - E[:, :u], axis=0)
+                      / A[:u]) <= 2 * FIELD_TOL
+
+
+def test_field_two_distant_clusters(g, W, orc):
+    """Two clusters 150 um apart: almost every source tile lies far from the
+    target block, so the expanded-square form carries nearly all pairs; the
+    clusters' mutual field is close to that of two point charges."""
+    n = 6000
+    a = W.gaussian_cloud(n, W.cloud_sigma(n), (480.0, 480.0, 200.0), 47, stream=8)
+    b = W.gaussian_cloud(n, W.cloud_sigma(n), (480.0, 480.0, 350.0), 47, stream=9)
+    x, y, z = (np.concatenate([a[i], b[i]]) for i in range(3))
+    p, d = dev_params(g, W)
+    E, st = gpu_field(g, p, x, y, z)
+    Eo, A = orc.field([x, y, z], with_magnitude=True)
+    ea, er = field_errors(E, Eo, A)
+    report(f"two clusters of {n}, 150 um apart", ea, er)
+    assert ea <= FIELD_TOL
+    # each cluster's own field sums to zero; the other one, 150 um away, pushes
+    # the lower cluster down and the upper one up, as a point charge would
+    point = orc.coulomb_constant(d["eps_r"]) * n / 150.0**2
+    assert abs(np.mean(Eo[2, :n]) + point) < 0.01 * point
+    assert abs(np.mean(Eo[2, n:]) - point) < 0.01 * point
+    assert np.mean(E[2, :n]) < 0.0 < np.mean(E[2, n:])
+
+
 def test_field_degenerate_sizes(g, W):
     p, d = dev_params(g, W)
     E, _ = gpu_field(g, p, [1.0], [2.0], [3.0])
