@@ -170,6 +170,49 @@ def test_batched_run_moments_and_images(g, W, orc):
           flush=True)
 
 
+def test_full_batch_one_step_sampled_events(g, W, orc, step_bound):
+    """The 4096-cloud batch of 1.8e7 holes, autotuned as the benchmark runs
+    it, one step: every hole of 12 events (the four largest, the smallest and
+    seven drawn at random) agrees with the oracle's FP64 step of that event
+    alone, to the displacement that the field tolerance allows."""
+    events = W.batch_of_clouds(4096, seed=1)
+    sizes = np.array([len(e[0]) for e in events])
+    off = np.concatenate([[0], np.cumsum(sizes)]).tolist()
+    x, y, z = (np.concatenate([e[k] for e in events]) for k in range(3))
+    d = dict(W.DEVICE)
+    ctx = g.gccd_init(g.Params.from_device(d))
+    try:
+        g.gccd_load_events(ctx, off, *gpu(x, y, z))
+        tpt, chunks, ms = g.gccd_autotune(ctx)
+        done, na = g.gccd_run(ctx, 10.0, 1)
+        pos, cs = g.gccd_positions(ctx, len(x))
+        pos, cs = pos.cpu().numpy(), cs.cpu().numpy()
+    finally:
+        g.gccd_destroy(ctx)
+    assert done == 1
+    order = np.argsort(sizes, kind="stable")
+    rest = np.setdiff1d(np.arange(len(sizes)), np.concatenate([order[-4:], order[:1]]))
+    pick = np.concatenate([order[-4:], order[:1],
+                           np.random.default_rng(17).choice(rest, 7, replace=False)])
+    per_field = step_bound(d, 10.0) * FIELD_TOL
+    worst, travelling = 0.0, 0
+    for e in pick:
+        sl = slice(off[e], off[e + 1])
+        o = orc.State(oracle_device(orc, d, int(e)), x[sl], y[sl], z[sl])
+        _, A = orc.field([o.x, o.y, o.z], with_magnitude=True)
+        o.run(10.0, 1)
+        assert np.array_equal(cs[sl], o.cstep), e
+        dr = np.linalg.norm(pos[:, sl] - np.stack([o.x, o.y, o.z]), axis=0)
+        ratio = dr / (per_field * A + 1e-9)
+        assert np.all(ratio <= 1.0), e
+        worst = max(worst, float(ratio.max()))
+        travelling += int(np.sum(o.cstep < 0))
+    print(f"[batch] 4096 events, tpt {tpt} chunks {chunks}: one step, "
+          f"{int(sizes[pick].sum())} holes of 12 events, worst |dr|/bound = {worst:.3e}",
+          flush=True)
+    assert travelling > 0
+
+
 def test_load_events_rejects_bad_offsets(g, W):
     ctx = g.gccd_init(g.Params.from_device(dict(W.DEVICE)))
     try:

@@ -239,25 +239,7 @@ def run_both(g, W, orc, w, steps, **kw):
     return (done, na, pos, cs, st), (odone, ona, o)
 
 
-def step_bound_per_field_error(orc, d, dt_ps):
-    """Displacement (um) per V/cm of field error in one step, from Eqs. (1)-(4).
-
-    Drift: v = mu(|E|) E has a Jacobian no larger than mu(0) (the velocity
-    rises monotonically with |E|), so drift moves by at most mu(0) dt per
-    V/cm.  Diffusion: sigma ~ sqrt(mu), so a field error dE changes the
-    displacement sigma g by sigma |g| |mu'| dE / (2 mu); |g| is at most 6.7
-    for normals drawn from 32-bit uniforms (sqrt(-2 ln 2^-32)), and the
-    largest |mu'|/mu is taken on a fine grid of |E| with a margin of 2."""
-    T, dt = d["temperature_K"], dt_ps * 1e-12
-    mu0 = orc.mobility(0.0, T, d["mobility_model"])
-    E = np.linspace(1.0, 2e5, 20001)
-    mu = np.array([orc.mobility(e, T, d["mobility_model"]) for e in E])
-    slope = 2.0 * float(np.max(np.abs(np.diff(mu) / np.diff(E)) / mu[1:]))
-    sigma0 = math.sqrt(2.0 * orc.thermal_voltage(T) * mu0 * dt) * 1e4
-    return mu0 * dt * 1e4 + sigma0 * 6.7 * slope / 2.0
-
-
-def test_step_full_size_every_hole(g, W, orc):
+def test_step_full_size_every_hole(g, W, orc, step_bound):
     """One whole step on the 1e5-hole cloud, in the launch configuration of
     the benchmark: every hole's new position agrees with the oracle's FP64
     step to the displacement that the field tolerance (1e-5 A_j) allows, plus
@@ -278,7 +260,7 @@ def test_step_full_size_every_hole(g, W, orc):
     assert (done, na) == (odone, ona) == (1, w.n)
     assert np.array_equal(cs, o.cstep)
     dr = np.linalg.norm(pos - np.stack([o.x, o.y, o.z]), axis=0)
-    bound = step_bound_per_field_error(orc, d, w.dt_ps) * FIELD_TOL * A + 1e-9
+    bound = step_bound(d, w.dt_ps) * FIELD_TOL * A + 1e-9
     print(f"[step] n={w.n}, one step: max |dr| = {dr.max():.3e} um, "
           f"max |dr|/bound = {np.max(dr / bound):.3e}", flush=True)
     assert np.all(dr <= bound)
