@@ -431,6 +431,31 @@ def test_image_edges_bit_exact(g, W, orc):
         assert int(counts.sum()) + nout == x.size
 
 
+def test_image_full_size_concentrated(g, W, orc):
+    """2^24 collected holes, most of them within a few pixels (millions of
+    increments of one counter) and 2 % sprayed over an area four times the
+    grid's width: the histogram and the outside count are bit-exact."""
+    n = 1 << 24
+    rng = np.random.default_rng(23)
+    wide = rng.random(n) < 0.02
+    x = np.where(wide, rng.uniform(-1440.0, 2400.0, n), rng.normal(480.0, 6.0, n))
+    y = np.where(wide, rng.uniform(-1440.0, 2400.0, n), rng.normal(480.0, 6.0, n))
+    z = np.zeros(n)
+    p, d = dev_params(g, W)
+    ctx = g.gccd_init(p)
+    try:
+        g.gccd_load(ctx, *gpu_tensors(x, y, z))
+        counts, nout = g.gccd_image(ctx, 0.0, 0.0, 15.0, 64, 64)
+        counts, nout = counts.cpu().numpy(), int(nout.cpu().numpy()[0])
+    finally:
+        g.gccd_destroy(ctx)
+    oc, onout = orc.image(x, y, np.zeros(n, np.int32), 0.0, 0.0, 15.0, 64, 64)
+    print(f"[image] n=2^24: fullest pixel {int(oc.max())}, outside {onout}", flush=True)
+    assert oc.max() > 1 << 20 and onout > 0
+    assert np.array_equal(counts, oc) and nout == onout
+    assert int(counts.sum()) + nout == n
+
+
 def test_nonfinite_position_is_reported(g, W):
     p, d = dev_params(g, W)
     ctx = g.gccd_init(p)
