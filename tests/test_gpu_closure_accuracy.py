@@ -55,7 +55,7 @@ def field(g, d, x, y, z, weights):
         g.gccd_destroy(ctx)
 
 
-@pytest.mark.parametrize("n,seed", [(30000, 2001), (100000, 2002), (300000, 2003)])
+@pytest.mark.parametrize("n,seed", [(30000, 2001), (100000, 2002), (300000, 2003), (1000000, 2005)])
 def test_closure_field_error(g, W, weights, n, seed):
     """Error of the closure's field against the exact path, relative to the rms
     of the exact far field (the part the network replaces; the rms of the
