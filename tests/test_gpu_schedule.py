@@ -175,3 +175,16 @@ def test_graph_recaptured_after_closure_buffers_change(g, W):
         assert np.array_equal(a, b), k
     st = res["graph"][1]
     assert st["closure_steps"] == 32 and st["graph_replays"] == 3 and st["graph_usable"] == 1
+
+
+def test_full_size_schedules_agree(g, W):
+    """The 1e5-hole cloud of the benchmark, two 32-step stretches: the three
+    schedules agree bit for bit at the size they are timed on."""
+    w = W.single_cloud(100000, seed=1)
+    d = dict(W.DEVICE)
+    runs = {s: stretches(g, d, w.x, w.y, w.z, s, n_stretch=2) for s in SCHEDULES}
+    compare(runs, "cloud 1e5")
+    st = runs["graph"][1]
+    print(f"[schedule] cloud n=100000: graph replays {st['graph_replays']}, usable "
+          f"{st['graph_usable']}", flush=True)
+    assert st["graph_usable"] == 1 and st["graph_replays"] == 2
