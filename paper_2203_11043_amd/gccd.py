@@ -13,7 +13,9 @@ from dataclasses import dataclass, fields
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgccd.so")
+# GCCD_LIB selects another build of the same library (the tests point it at the
+# host-sanitized variant)
+LIB_PATH = os.environ.get("GCCD_LIB") or os.path.join(_HERE, "libgccd.so")
 ABI_VERSION = 3
 CLOSURE_WEIGHTS = 290784      # GCCD_CLOSURE_WEIGHTS
 
