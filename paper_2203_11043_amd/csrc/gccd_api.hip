@@ -85,6 +85,7 @@ struct gccd_ctx {
     double* ps[3] = {nullptr, nullptr, nullptr};
     double* tile_box = nullptr;
     float* part = nullptr;
+    unsigned long long* close = nullptr;  // [3][n] fixed-point sums of exactly summed close pairs
     uint32_t* ev_off_d = nullptr;
     uint32_t* ev_tile_d = nullptr;
     uint32_t* tile_event_d = nullptr;
@@ -93,8 +94,6 @@ struct gccd_ctx {
     FieldItem* items_d = nullptr;
     size_t items_cap = 0;
     uint32_t n_items = 0;
-    void* sort_tmp = nullptr;
-    size_t sort_tmp_bytes = 0;
     uint32_t* meta = nullptr;
     uint32_t* host_meta = nullptr;    // pinned
     uint32_t* host_active = nullptr;  // pinned [E]
@@ -218,18 +217,17 @@ void free_buffers(gccd_ctx* c) {
     for (auto& q : c->ps) dfree(q);
     dfree(c->tile_box);
     dfree(c->part);
+    dfree(c->close);
     dfree(c->ev_off_d);
     dfree(c->ev_tile_d);
     dfree(c->tile_event_d);
     dfree(c->ev_active_d);
     dfree(c->ev_chunks_d);
     dfree(c->items_d);
-    dfree(c->sort_tmp);
     hfree(c->host_active);
     hfree(c->host_items);
     c->items_cap = 0;
     c->part_groups = 0;
-    c->sort_tmp_bytes = 0;
     c->loaded = false;
 }
 
@@ -293,6 +291,24 @@ uint64_t balance_chunks(uint64_t tiles, uint64_t s0, uint64_t cap) {
 // workgroup slot.  The first T1 = T - T2 tiles keep the balanced round-robin
 // split.  The layers change which tiles share a partial sum, not the pairs
 // summed.
+// The tail layer of one event of `tiles` source tiles, `blocks` target
+// blocks and s first-layer chunks, given the tile-units of tail work still
+// wanted: fills chunks (both layers), tail (its chunks) and split (its first
+// tile) and returns the work it takes, or 0 when the event gets no tail.
+int64_t event_tail(uint64_t tiles, uint64_t blocks, uint64_t s, uint64_t cap, int64_t need,
+                   int32_t* chunks, int32_t* tail, uint32_t* split) {
+    uint64_t t2 = std::min<uint64_t>(tiles / 4, ((uint64_t)need + blocks - 1) / blocks);
+    t2 = std::max<uint64_t>(t2, 1);
+    const uint64_t s2 = t2;  // one tile per tail chunk
+    if (s2 + 1 > cap) return 0;
+    const uint64_t t1 = tiles - t2;
+    const uint64_t s1 = balance_chunks(t1, std::min<uint64_t>({s, cap - s2, t1}), cap - s2);
+    *chunks = (int32_t)(s1 + s2);
+    *tail = (int32_t)s2;
+    *split = (uint32_t)t1;
+    return (int64_t)(blocks * t2);
+}
+
 void plan_tail(gccd_ctx* c, uint64_t cap) {
     c->tail_h.assign(c->n_events, 0);
     c->split_h.assign(c->n_events, 0);
@@ -315,17 +331,20 @@ void plan_tail(gccd_ctx* c, uint64_t cap) {
         const uint64_t tiles = (ne + kTile - 1) / kTile, blocks = (ne + per - 1) / per;
         const uint64_t s = (uint64_t)c->chunks_h[e];
         if ((tiles + s - 1) / s < 4) break;  // smaller events have short items already
-        uint64_t t2 = std::min<uint64_t>(tiles / 4, ((uint64_t)need + blocks - 1) / blocks);
-        t2 = std::max<uint64_t>(t2, 1);
-        const uint64_t s2 = t2;  // one tile per tail chunk
-        if (s2 + 1 > cap) continue;
-        const uint64_t t1 = tiles - t2;
-        const uint64_t s1 = balance_chunks(t1, std::min<uint64_t>({s, cap - s2, t1}), cap - s2);
-        c->chunks_h[e] = (int32_t)(s1 + s2);
-        c->tail_h[e] = (int32_t)s2;
-        c->split_h[e] = (uint32_t)t1;
-        need -= (int64_t)(blocks * t2);
+        need -= event_tail(tiles, blocks, s, cap, need, &c->chunks_h[e], &c->tail_h[e],
+                           &c->split_h[e]);
     }
+}
+
+// The automatic first-layer chunk count of an event of ne holes when the
+// load has tblocks target blocks in all.
+uint64_t auto_chunks(uint64_t ne, uint64_t tblocks, int n_cu, uint64_t cap) {
+    const uint64_t tiles = (ne + kTile - 1) / kTile;
+    const uint64_t want = (uint64_t)n_cu * 64;
+    uint64_t s = std::max<uint64_t>((ne + 3071) / 3072, (want + tblocks - 1) / tblocks);
+    s = std::min<uint64_t>(s, std::max<uint64_t>(1, tiles));
+    s = std::max<uint64_t>(s, 1);
+    return balance_chunks(tiles, std::min<uint64_t>(s, cap), cap);
 }
 
 void choose_chunks(gccd_ctx* c) {
@@ -333,7 +352,6 @@ void choose_chunks(gccd_ctx* c) {
     for (uint32_t e = 0; e < c->n_events; ++e)
         tblocks += (c->off_h[e + 1] - c->off_h[e] + kFieldThreads * c->tpt - 1) /
                    (kFieldThreads * c->tpt);
-    const uint64_t want = (uint64_t)c->n_cu * 64;
     c->chunks_h.assign(c->n_events, 1);
     c->groups_h.assign(c->n_events, 1);
     c->max_chunks = 1;
@@ -348,10 +366,7 @@ void choose_chunks(gccd_ctx* c) {
             // at most one chunk per tile: small events of a batch get no empty chunks
             s = std::min<uint64_t>((uint64_t)c->chunks_fixed, std::max<uint64_t>(1, tiles));
         } else {
-            s = std::max<uint64_t>((ne + 3071) / 3072, (want + tblocks - 1) / tblocks);
-            s = std::min<uint64_t>(s, std::max<uint64_t>(1, tiles));
-            s = std::max<uint64_t>(s, 1);
-            s = balance_chunks(tiles, std::min<uint64_t>(s, cap), cap);
+            s = auto_chunks(ne, tblocks, c->n_cu, cap);
         }
         s = std::min<uint64_t>(s, cap);
         c->chunks_h[e] = (int32_t)s;
@@ -437,7 +452,20 @@ int size_chunk_buffers(gccd_ctx* c) {
     return GCCD_OK;
 }
 
+// The close-pair sums of the default precision: allocated with the partial
+// sums, zero between launches (every consumer of a field launch clears the
+// slots it reads).
+int ensure_close(gccd_ctx* c) {
+    if (c->close) return GCCD_OK;
+    const size_t words = 3 * (size_t)c->n;
+    if (hipMalloc(&c->close, words * sizeof(unsigned long long)) != hipSuccess)
+        return fail(c, GCCD_E_NOMEM, "close-pair sum allocation failed");
+    GCCD_HIP(c, launch_fill_u32(reinterpret_cast<uint32_t*>(c->close), 2 * words, 0u, c->stream));
+    return GCCD_OK;
+}
+
 int ensure_part(gccd_ctx* c) {
+    if (int r = ensure_close(c); r != GCCD_OK) return r;
     if (c->part_groups >= c->max_groups) return GCCD_OK;
     drop_graph(c);
     dfree(c->part);
@@ -502,6 +530,11 @@ FieldArgs field_args(const gccd_ctx* c, bool targets_all) {
     fa.n_items = c->sched + kSchedItems;
     fa.queue = c->sched + kSchedQueue;
     fa.near_compensated = c->near_compensated ? 1 : 0;
+    const double eps2 = c->p.softening_um * c->p.softening_um;
+    fa.acc2 = (float)((kExactRadius * kExactRadius + 1.0) * eps2);
+    fa.acc_box2 = kExactRadius * kExactRadius * eps2;
+    fa.acc_scale = std::ldexp(eps2, kExactShift);
+    fa.close = c->close;
     return fa;
 }
 
@@ -521,9 +554,7 @@ uint32_t queue_grid(gccd_ctx* c) {
 // keys[cur], count each event's travelling holes, gather the positions.
 int finish_list(gccd_ctx* c) {
     const uint32_t n = (uint32_t)c->n;
-    const uint32_t end_bit = c->kl.lbits + kCurveBits + 1 + c->kl.ebits;
-    GCCD_HIP(c, sort_keys(c->sort_tmp, c->sort_tmp_bytes, c->keys[c->cur ^ 1], c->keys[c->cur], n,
-                          end_bit, c->stream));
+    GCCD_HIP(c, sort_keys(c->keys[c->cur ^ 1], c->keys[c->cur], n, c->stream));
     GCCD_HIP(c, launch_count(c->keys[c->cur], c->ev_off_d, c->n_events, c->kl,
                              c->p.collected_are_sources,
                              c->ev_active_d,
@@ -947,13 +978,6 @@ int gccd_load_events(gccd_ctx* c, int32_t n_events, const int64_t* offsets, cons
         free_buffers(c);
         return fail(c, GCCD_E_NOMEM, "gccd_load_events: device allocation failed");
     }
-    size_t need = 0;
-    GCCD_HIP(c, sort_keys_storage((uint32_t)n, kl.lbits + kCurveBits + 1 + kl.ebits, &need));
-    if (hipMalloc(&c->sort_tmp, std::max<size_t>(need, 1)) != hipSuccess) {
-        free_buffers(c);
-        return fail(c, GCCD_E_NOMEM, "gccd_load_events: sort storage allocation failed");
-    }
-    c->sort_tmp_bytes = std::max<size_t>(need, 1);
     GCCD_HIP(c, hipMemcpyAsync(c->ev_off_d, c->off_h.data(), (E + 1) * sizeof(uint32_t),
                                hipMemcpyHostToDevice, c->stream));
     GCCD_HIP(c, hipMemcpyAsync(c->ev_tile_d, c->tile_h.data(), (E + 1) * sizeof(uint32_t),
@@ -962,7 +986,8 @@ int gccd_load_events(gccd_ctx* c, int32_t n_events, const int64_t* offsets, cons
                                tile_event.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
                                c->stream));
     {
-        int r = size_chunk_buffers(c);  // synchronises: tile_event may go out of scope
+        int r = c->p.coulomb ? ensure_close(c) : GCCD_OK;
+        if (r == GCCD_OK) r = size_chunk_buffers(c);  // synchronises: tile_event may go out of scope
         if (r != GCCD_OK) {
             free_buffers(c);
             return r;
@@ -1128,9 +1153,10 @@ int gccd_closure_parts(gccd_ctx* c, double* near_x, double* near_y, double* near
     if (r != GCCD_OK) return r;
     const int S = c->near_chunks;
     GCCD_HIP(c, launch_field_finish(c->part, n, c->ev_chunks_d, 0, S, c->keys[c->cur], c->ev_off_d,
-                                    c->kl, n, c->K, near_x, near_y, near_z, c->stream));
+                                    c->kl, n, c->K, nullptr, 0.0, near_x, near_y, near_z,
+                                    c->stream));
     GCCD_HIP(c, launch_field_finish(c->part, n, c->ev_chunks_d, S, 1, c->keys[c->cur], c->ev_off_d,
-                                    c->kl, n, c->K, far_x, far_y, far_z, c->stream));
+                                    c->kl, n, c->K, nullptr, 0.0, far_x, far_y, far_z, c->stream));
     GCCD_HIP(c, hipMemcpyAsync(rho, c->rho_f32, (size_t)kGridNodes * sizeof(float),
                                hipMemcpyDeviceToDevice, c->stream));
     GCCD_HIP(c, hipMemcpyAsync(grid, c->gp, 4 * sizeof(double), hipMemcpyDeviceToDevice,
@@ -1184,6 +1210,11 @@ int gccd_autotune(gccd_ctx* c, int32_t* targets_per_thread, int32_t* source_chun
             }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
+        // the timed launches left close-pair sums that nothing consumed
+        if (r == GCCD_OK && c->close &&
+            launch_fill_u32(reinterpret_cast<uint32_t*>(c->close), 6 * (uint64_t)c->n, 0u,
+                            c->stream) != hipSuccess)
+            r = fail(c, GCCD_E_DEVICE, "gccd_autotune: clearing the close-pair sums failed");
         if (r != GCCD_OK) {
             free_buffers(c);
             return r;
@@ -1273,6 +1304,8 @@ int gccd_run(gccd_ctx* c, double dt_ps, int64_t max_steps, int64_t* steps_done,
     sa.event0 = c->p.event;
     sa.key0 = (uint32_t)c->p.seed;
     sa.key1 = (uint32_t)(c->p.seed >> 32);
+    sa.close = c->list_mode ? c->close : nullptr;
+    sa.close_unit = std::ldexp(1.0 / (c->p.softening_um * c->p.softening_um), -kExactShift);
     sa.pending = reinterpret_cast<const unsigned long long*>(c->meta + kMetaPending);
     sa.stats = reinterpret_cast<unsigned long long*>(c->meta + kMetaStats);
     sa.misc = reinterpret_cast<int32_t*>(c->meta + kMetaFlag);
@@ -1404,8 +1437,10 @@ int gccd_field(gccd_ctx* c, double* ex, double* ey, double* ez) {
         FieldArgs fa = field_args(c, true);
         GCCD_HIP(c, launch_field(fa, c->tpt, c->precision, c->n_items, queue_grid(c), c->stream));
     }
-    GCCD_HIP(c, launch_field_finish(c->part, n, c->ev_chunks_d, 0, 0, c->keys[c->cur],
-                                    c->ev_off_d, c->kl, n, c->K, ex, ey, ez, c->stream));
+    GCCD_HIP(c, launch_field_finish(
+                    c->part, n, c->ev_chunks_d, 0, 0, c->keys[c->cur], c->ev_off_d, c->kl, n, c->K,
+                    c->close, std::ldexp(1.0 / (c->p.softening_um * c->p.softening_um), -kExactShift),
+                    ex, ey, ez, c->stream));
     GCCD_HIP(c, hipStreamSynchronize(c->stream));  // host_items may be rebuilt next
     return GCCD_OK;
 }

@@ -69,7 +69,22 @@ struct FieldArgs {
     uint32_t* queue;            // persistent launch: [0] next item (zero before the launch)
     int32_t near_compensated;   // one target per thread, default precision: tiles within
                                 // rho/4 take the compensated difference (small launches)
+    // Close pairs summed exactly (default precision): a pair with r^2 + eps^2 below
+    // acc2 has its term formed in FP64 and added, in fixed point, to the target's
+    // slot of `close` ([3][pstride] 64-bit integers, zero before the launch; the
+    // consumer of the field reads and clears it); its FP32 term is dropped.
+    float acc2;                 // (kExactRadius^2 + 1) eps^2
+    double acc_box2;            // (kExactRadius eps)^2: a tile box at least this far from
+                                // the targets' box holds no such pair
+    double acc_scale;           // fixed-point units per um^-2
+    unsigned long long* close;
 };
+
+// Pairs closer than kExactRadius softening lengths are summed exactly (see
+// FieldArgs::close); the fixed-point unit is 2^-kExactShift / eps^2, so the
+// largest term of Eq. (6), 0.385 / eps^2, takes 2^38.6 units.
+constexpr double kExactRadius = 32.0;
+constexpr int kExactShift = 40;
 
 // Everything the per-carrier update of one step needs.
 struct StepArgs {
@@ -105,6 +120,9 @@ struct StepArgs {
     const uint32_t* cnt_in;   // carrier mode: travelling holes at the start of the step
     uint32_t* cnt_out;        // carrier mode: ... of the next step (zeroed beforehand)
     uint32_t* cnt_clear;      // carrier mode: counter of the step after next
+    unsigned long long* close;  // list mode: the exactly summed close terms by slot
+                                // ([3][pstride]); read and cleared
+    double close_unit;          // um^-2 per fixed-point unit of close
     const unsigned long long* pending;  // list mode: [0] holes, [1] pairs of this step
     unsigned long long* stats;  // [0] carrier-steps, [1] pair interactions
     int32_t* misc;              // [0] non-finite flag, [1] step after the last busy one
@@ -136,10 +154,13 @@ hipError_t launch_count(const uint64_t* keys, const uint32_t* ev_off, uint32_t n
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
 // Sums the partial groups [g0, g0 + ev_chunks[e]) (or [g0, g0 + groups) when
 // groups > 0) of every slot and writes K times the sum in carrier order.
+// close (may be NULL): the exactly summed close terms by slot, added in and
+// cleared (close_unit um^-2 per unit).
 hipError_t launch_field_finish(const float* part, uint32_t pstride, const int32_t* ev_chunks,
                                int g0, int groups, const uint64_t* keys, const uint32_t* ev_off,
-                               KeyLayout kl, uint32_t n, double K, double* ex, double* ey,
-                               double* ez, hipStream_t s);
+                               KeyLayout kl, uint32_t n, double K, unsigned long long* close,
+                               double close_unit, double* ex, double* ey, double* ez,
+                               hipStream_t s);
 hipError_t launch_image(const double* x, const double* y, const int32_t* cstep,
                         const uint32_t* ev_of, uint32_t n, int per_event, double x0, double y0,
                         double pitch, int32_t nx, int32_t ny, uint32_t* counts,
@@ -201,9 +222,8 @@ hipError_t launch_far(const float* F, const GridParams* gp, const double* px, co
                       const double* pz, uint32_t nt, float* ox, float* oy, float* oz,
                       hipStream_t s);
 
-// Sorting of key lists (rocPRIM radix sort; storage provided by the caller).
-hipError_t sort_keys_storage(uint32_t n, uint32_t end_bit, size_t* bytes);
-hipError_t sort_keys(void* tmp, size_t tmp_bytes, const uint64_t* in, uint64_t* out,
-                     uint32_t n, uint32_t end_bit, hipStream_t s);
+// Sorts the n keys of `keys` into `out` (merge sort, gccd_sort.hip); `keys`
+// is used as the other buffer of the merge levels and left in no useful order.
+hipError_t sort_keys(uint64_t* keys, uint64_t* out, uint32_t n, hipStream_t s);
 
 }  // namespace gccd

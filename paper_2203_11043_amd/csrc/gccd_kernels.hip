@@ -120,6 +120,56 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
+// Pairs closer than kExactRadius softening lengths are summed exactly.  The
+// pair loop only records them (exact_push: the target's index in the item's
+// block and the source's slot in its event, in an LDS list of the work item)
+// and drops their FP32 terms; at the end of the item exact_flush forms each
+// recorded term in FP64 from the FP64 positions, as Eq. (6) defines it, and
+// adds it in fixed point to the target's slot of the close sums.  Integer
+// addition is associative, so the sums do not depend on the order in which
+// work items finish.  Keeping the FP64 work out of the pair loop keeps its
+// registers (and the kernel's occupancy) as they are.  A pair that finds the
+// list full keeps its FP32 term.
+constexpr int kExactCap = 512;
+
+struct ExactList {
+    uint32_t n;
+    uint32_t tgt[kExactCap];
+    uint32_t src[kExactCap];
+};
+
+__device__ __forceinline__ bool exact_push(ExactList& L, uint32_t tgt, uint32_t src) {
+    const uint32_t i = atomicAdd(&L.n, 1u);
+    if (i >= (uint32_t)kExactCap) return false;
+    L.tgt[i] = tgt;
+    L.src[i] = src;
+    return true;
+}
+
+// Called by every lane of the workgroup after the item's last barrier;
+// targets of the item are slots off + tbase + tgt, sources slots off + src.
+// Leaves the list empty for the next item (whose first barrier orders the
+// clearing before any push).
+__device__ __forceinline__ void exact_flush(const FieldArgs& a, ExactList& L, uint32_t off,
+                                            uint32_t tbase) {
+    const uint32_t cnt = min(L.n, (uint32_t)kExactCap);
+    if (cnt == 0) return;  // uniform: every lane reads L.n after the same barrier
+    for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+        const uint32_t t = off + tbase + L.tgt[i], s = off + L.src[i];
+        const double dx = a.px[t] - a.px[s], dy = a.py[t] - a.py[s], dz = a.pz[t] - a.pz[s];
+        double q = fma(dx, dx, a.eps2d);
+        q = fma(dy, dy, q);
+        q = fma(dz, dz, q);
+        const double w = a.acc_scale / (q * sqrt(q));
+        unsigned long long* c = a.close + t;
+        atomicAdd(c, (unsigned long long)__double2ll_rn(dx * w));
+        atomicAdd(c + a.pstride, (unsigned long long)__double2ll_rn(dy * w));
+        atomicAdd(c + 2 * (size_t)a.pstride, (unsigned long long)__double2ll_rn(dz * w));
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) L.n = 0;
+}
+
 // ---------------------------------------------------------------------------
 // Eq. (6):  E_j = K sum_i r_ij / (|r_ij|^2 + eps^2)^{3/2},  r_ij = r_j - r_i,
 // summed over the sources of the target's own event.
@@ -151,6 +201,15 @@ __device__ __forceinline__ double wave_max(double v) {
 // Each tile's contributions are summed separately and then added to the
 // running sum (blocked summation).
 //
+// Pairs closer than kExactRadius eps (32 nm at eps = 1 nm) are the one case
+// where that relative bound is not enough: their terms reach 0.385 / eps^2,
+// tens to hundreds of times the rms field of a cloud, and an FP32 term and the
+// FP32 additions that follow it would carry about 10u of that into the
+// target's field.  They are summed exactly instead (exact_push): the close-pair
+// radius is at least that distance, so these pairs always take the checked
+// path, and tiles that can hold them are never summed in the unchecked or the
+// expanded form.
+//
 // The other GCCD_PRECISION_* modes change the origin (one per event, or
 // none: absolute coordinates) or the difference formation (hi parts only,
 // or hi and lo for every pair); they exist to measure those choices.
@@ -164,8 +223,10 @@ enum : int {
 };
 
 // CUT: the term counts only when r^2 + eps^2 < cut2 (the near part of a
-// near/far split); 2 more VALU per pair.
-template <int TPT, int DIFF, bool CUT = false>
+// near/far split); 2 more VALU per pair.  EXACT (with kDiffNear): pairs with
+// r^2 + eps^2 below ap->acc2 are recorded in *xl (target t of the lane is
+// tgt0 + t * kFieldThreads of the item's block, the source src of the event).
+template <int TPT, int DIFF, bool CUT = false, bool EXACT = false>
 __device__ __forceinline__ void pair_terms(const float* __restrict__ lxp,
                                            const float* __restrict__ lyp,
                                            const float* __restrict__ lzp, uint32_t k, float shx,
@@ -175,7 +236,9 @@ __device__ __forceinline__ void pair_terms(const float* __restrict__ lxp,
                                            const float (&tly)[TPT], const float (&tlz)[TPT],
                                            float eps2, const float (&rc2)[TPT], float (&ax)[TPT],
                                            float (&ay)[TPT], float (&az)[TPT],
-                                           float cut2 = 0.0f) {
+                                           float cut2 = 0.0f, const FieldArgs* ap = nullptr,
+                                           ExactList* xl = nullptr, uint32_t tgt0 = 0u,
+                                           uint32_t src = 0u) {
     float dx[TPT], dy[TPT], dz[TPT], r2[TPT];
     bool near = false;
 #pragma unroll
@@ -208,6 +271,16 @@ __device__ __forceinline__ void pair_terms(const float* __restrict__ lxp,
                 r2[t] = __builtin_fmaf(dz[t], dz[t], r2[t]);
             }
         }
+        if (EXACT) {
+            // rc2 is at least acc2 for a target and 0 for a padding slot; a pair
+            // at distance 0 has a zero term and stays in the FP32 sum
+#pragma unroll
+            for (int t = 0; t < TPT; ++t) {
+                if (r2[t] < fminf(ap->acc2, rc2[t]) && r2[t] > eps2 &&
+                    exact_push(*xl, tgt0 + (uint32_t)(t * kFieldThreads), src))
+                    dx[t] = dy[t] = dz[t] = 0.0f;
+            }
+        }
     }
 #pragma unroll
     for (int t = 0; t < TPT; ++t) {
@@ -223,7 +296,7 @@ __device__ __forceinline__ void pair_terms(const float* __restrict__ lxp,
 }
 
 // All pairs of one staged tile (cnt sources) with the lane's TPT targets.
-template <int TPT, int DIFF, bool CUT = false>
+template <int TPT, int DIFF, bool CUT = false, bool EXACT = false>
 __device__ __forceinline__ void tile_terms(const float* __restrict__ hxp,
                                            const float* __restrict__ hyp,
                                            const float* __restrict__ hzp,
@@ -235,7 +308,9 @@ __device__ __forceinline__ void tile_terms(const float* __restrict__ hxp,
                                            const float (&tly)[TPT], const float (&tlz)[TPT],
                                            float eps2, const float (&rc2)[TPT], float (&bx)[TPT],
                                            float (&by)[TPT], float (&bz)[TPT],
-                                           float cut2 = 0.0f) {
+                                           float cut2 = 0.0f, const FieldArgs* ap = nullptr,
+                                           ExactList* xl = nullptr, uint32_t tgt0 = 0u,
+                                           uint32_t src0 = 0u) {
     uint32_t k = 0;
     for (; k + 4 <= cnt; k += 4) {
         const float4 hx4 = *reinterpret_cast<const float4*>(hxp + k);
@@ -247,22 +322,22 @@ __device__ __forceinline__ void tile_terms(const float* __restrict__ hxp,
             ly4 = *reinterpret_cast<const float4*>(lyp + k);
             lz4 = *reinterpret_cast<const float4*>(lzp + k);
         }
-        pair_terms<TPT, DIFF, CUT>(lxp, lyp, lzp, k + 0, hx4.x, hy4.x, hz4.x, lx4.x, ly4.x, lz4.x, thx,
+        pair_terms<TPT, DIFF, CUT, EXACT>(lxp, lyp, lzp, k + 0, hx4.x, hy4.x, hz4.x, lx4.x, ly4.x, lz4.x, thx,
                               thy, thz, tlx, tly, tlz, eps2, rc2, bx, by, bz,
-                                   cut2);
-        pair_terms<TPT, DIFF, CUT>(lxp, lyp, lzp, k + 1, hx4.y, hy4.y, hz4.y, lx4.y, ly4.y, lz4.y, thx,
+                                   cut2, ap, xl, tgt0, src0 + k + 0);
+        pair_terms<TPT, DIFF, CUT, EXACT>(lxp, lyp, lzp, k + 1, hx4.y, hy4.y, hz4.y, lx4.y, ly4.y, lz4.y, thx,
                               thy, thz, tlx, tly, tlz, eps2, rc2, bx, by, bz,
-                                   cut2);
-        pair_terms<TPT, DIFF, CUT>(lxp, lyp, lzp, k + 2, hx4.z, hy4.z, hz4.z, lx4.z, ly4.z, lz4.z, thx,
+                                   cut2, ap, xl, tgt0, src0 + k + 1);
+        pair_terms<TPT, DIFF, CUT, EXACT>(lxp, lyp, lzp, k + 2, hx4.z, hy4.z, hz4.z, lx4.z, ly4.z, lz4.z, thx,
                               thy, thz, tlx, tly, tlz, eps2, rc2, bx, by, bz,
-                                   cut2);
-        pair_terms<TPT, DIFF, CUT>(lxp, lyp, lzp, k + 3, hx4.w, hy4.w, hz4.w, lx4.w, ly4.w, lz4.w, thx,
+                                   cut2, ap, xl, tgt0, src0 + k + 2);
+        pair_terms<TPT, DIFF, CUT, EXACT>(lxp, lyp, lzp, k + 3, hx4.w, hy4.w, hz4.w, lx4.w, ly4.w, lz4.w, thx,
                               thy, thz, tlx, tly, tlz, eps2, rc2, bx, by, bz,
-                                   cut2);
+                                   cut2, ap, xl, tgt0, src0 + k + 3);
     }
     for (; k < cnt; ++k) {
-        pair_terms<TPT, DIFF, CUT>(lxp, lyp, lzp, k, hxp[k], hyp[k], hzp[k], lxp[k], lyp[k], lzp[k],
-                                   thx, thy, thz, tlx, tly, tlz, eps2, rc2, bx, by, bz, cut2);
+        pair_terms<TPT, DIFF, CUT, EXACT>(lxp, lyp, lzp, k, hxp[k], hyp[k], hzp[k], lxp[k], lyp[k], lzp[k],
+                                   thx, thy, thz, tlx, tly, tlz, eps2, rc2, bx, by, bz, cut2, ap, xl, tgt0, src0 + k);
     }
 }
 
@@ -272,6 +347,7 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles(FieldArgs a) {
     __shared__ double box[6][kFieldThreads / 64];
     __shared__ double ebox[6][kFieldThreads / 64];  // EVENT mode: the event's source box
     __shared__ double tbox[2][6];  // bounding box of the staged source tile
+    __shared__ ExactList xl;       // default precision: close pairs of the item
 
     const FieldItem it = a.items[blockIdx.x];
     const uint32_t off = a.ev_off[it.event];
@@ -294,6 +370,7 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles(FieldArgs a) {
     const uint32_t t_first = it.first;
     const uint32_t t_end = min(it.end, ntiles);
     const int tid = threadIdx.x;
+    if (tid == 0) xl.n = 0;  // ordered before any push by the barrier below
 
     // targets and their bounding box
     double px[TPT], py[TPT], pz[TPT];
@@ -409,6 +486,7 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles(FieldArgs a) {
         rc2[t] = ts < nt ? 0.0625f * (float)((double)thx[t] * thx[t] + (double)thy[t] * thy[t] +
                                              (double)thz[t] * thz[t])
                          : 0.0f;
+        if (PREC == GCCD_PRECISION_DEFAULT && ts < nt) rc2[t] = fmaxf(rc2[t], a.acc2);
         ax[t] = 0.0f;
         ay[t] = 0.0f;
         az[t] = 0.0f;
@@ -467,7 +545,7 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles(FieldArgs a) {
         const double gx = fmax(0.0, fmax(tb[0] - hi_x, lo_x - tb[3]));
         const double gy = fmax(0.0, fmax(tb[1] - hi_y, lo_y - tb[4]));
         const double gz = fmax(0.0, fmax(tb[2] - hi_z, lo_z - tb[5]));
-        const bool far_tile = gx * gx + gy * gy + gz * gz >= rc2d;
+        const bool far_tile = gx * gx + gy * gy + gz * gz >= fmax(rc2d, a.acc_box2);
         if (PREC == GCCD_PRECISION_COMPENSATED) {
             tile_terms<TPT, kDiffAll>(hxp, hyp, hzp, lxp, lyp, lzp, cnt, thx, thy, thz, tlx, tly,
                                       tlz, a.eps2, rc2, bx, by, bz);
@@ -475,8 +553,9 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles(FieldArgs a) {
             tile_terms<TPT, kDiffHi>(hxp, hyp, hzp, lxp, lyp, lzp, cnt, thx, thy, thz, tlx, tly,
                                      tlz, a.eps2, rc2, bx, by, bz);
         } else {
-            tile_terms<TPT, kDiffNear>(hxp, hyp, hzp, lxp, lyp, lzp, cnt, thx, thy, thz, tlx, tly,
-                                       tlz, a.eps2, rc2, bx, by, bz);
+            tile_terms<TPT, kDiffNear, false, true>(hxp, hyp, hzp, lxp, lyp, lzp, cnt, thx, thy,
+                                                    thz, tlx, tly, tlz, a.eps2, rc2, bx, by, bz,
+                                                    0.0f, &a, &xl, (uint32_t)tid, t * kTile);
         }
 #pragma unroll
         for (int u = 0; u < TPT; ++u) {
@@ -489,6 +568,7 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles(FieldArgs a) {
         buf ^= 1;
     }
 
+    if (PREC == GCCD_PRECISION_DEFAULT) exact_flush(a, xl, off, tbase);
     float* outx = a.part + (size_t)(chunk * 3 + 0) * a.pstride + off;
     float* outy = a.part + (size_t)(chunk * 3 + 1) * a.pstride + off;
     float* outz = a.part + (size_t)(chunk * 3 + 2) * a.pstride + off;
@@ -529,8 +609,12 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles(FieldArgs a) {
 // the close pairs -- and whole small events, which have no far tiles -- are
 // summed bit for bit as by that kernel.  Small loads differ on purpose: see
 // COMP below.
+// CHECK: pairs closer than the lane's radius (rc2, at least acc2 for a target,
+// 0 for a padding lane) are recomputed with the lo parts, and those below acc2
+// (source slot src of the event) are recorded for exact summation.
 template <bool CHECK>
-__device__ __forceinline__ void diff_pair(const float* __restrict__ lxp,
+__device__ __forceinline__ void diff_pair(const FieldArgs& a, ExactList& xl, uint32_t src,
+                                          const float* __restrict__ lxp,
                                           const float* __restrict__ lyp,
                                           const float* __restrict__ lzp, uint32_t k, float m2x,
                                           float m2y, float m2z, float thx, float thy, float thz,
@@ -553,6 +637,8 @@ __device__ __forceinline__ void diff_pair(const float* __restrict__ lxp,
             r2 = __builtin_fmaf(dy, dy, r2);
             r2 = __builtin_fmaf(dz, dz, r2);
         }
+        if (r2 < fminf(a.acc2, rc2) && r2 > eps2 && exact_push(xl, threadIdx.x, src))
+            dx = dy = dz = 0.0f;
     }
     const float inv = __builtin_amdgcn_rsqf(r2);
     const float w = inv * inv * inv;
@@ -562,17 +648,24 @@ __device__ __forceinline__ void diff_pair(const float* __restrict__ lxp,
 }
 
 // Difference form with the lo parts in every pair (the compensated
-// difference of the COMPENSATED mode), branch-free.
-__device__ __forceinline__ void comp_pair(float m2x, float m2y, float m2z, float lx, float ly,
-                                          float lz, float thx, float thy, float thz, float tlx,
-                                          float tly, float tlz, float eps2, float& bx, float& by,
+// difference of the COMPENSATED mode); pairs below acc2 are recorded for
+// exact summation.
+__device__ __forceinline__ void comp_pair(const FieldArgs& a, ExactList& xl, uint32_t src,
+                                          float m2x, float m2y,
+                                          float m2z, float lx, float ly, float lz, float thx,
+                                          float thy, float thz, float tlx, float tly, float tlz,
+                                          float eps2, float rc2, float& bx, float& by,
                                           float& bz) {
-    const float dx = __builtin_fmaf(m2x, 0.5f, thx) + (tlx - lx);
-    const float dy = __builtin_fmaf(m2y, 0.5f, thy) + (tly - ly);
-    const float dz = __builtin_fmaf(m2z, 0.5f, thz) + (tlz - lz);
+    float dx = __builtin_fmaf(m2x, 0.5f, thx) + (tlx - lx);
+    float dy = __builtin_fmaf(m2y, 0.5f, thy) + (tly - ly);
+    float dz = __builtin_fmaf(m2z, 0.5f, thz) + (tlz - lz);
     float r2 = __builtin_fmaf(dx, dx, eps2);
     r2 = __builtin_fmaf(dy, dy, r2);
     r2 = __builtin_fmaf(dz, dz, r2);
+    if (__builtin_expect(__ballot(r2 < fminf(a.acc2, rc2)) != 0ull, 0)) {
+        if (r2 < fminf(a.acc2, rc2) && r2 > eps2 && exact_push(xl, threadIdx.x, src))
+            dx = dy = dz = 0.0f;
+    }
     const float inv = __builtin_amdgcn_rsqf(r2);
     const float w = inv * inv * inv;
     bx = __builtin_fmaf(dx, w, bx);
@@ -580,12 +673,13 @@ __device__ __forceinline__ void comp_pair(float m2x, float m2y, float m2z, float
     bz = __builtin_fmaf(dz, w, bz);
 }
 
-__device__ __forceinline__ void comp_tile(const float* __restrict__ mxp, const float* __restrict__ myp,
+__device__ __forceinline__ void comp_tile(const FieldArgs& a, ExactList& xl, uint32_t src0,
+                                          const float* __restrict__ mxp, const float* __restrict__ myp,
                                           const float* __restrict__ mzp, const float* __restrict__ lxp,
                                           const float* __restrict__ lyp, const float* __restrict__ lzp,
                                           uint32_t cnt, float thx, float thy, float thz, float tlx,
-                                          float tly, float tlz, float eps2, float& bx, float& by,
-                                          float& bz) {
+                                          float tly, float tlz, float eps2, float rc2, float& bx,
+                                          float& by, float& bz) {
     uint32_t k = 0;
     for (; k + 4 <= cnt; k += 4) {
         const float4 x4 = *reinterpret_cast<const float4*>(mxp + k);
@@ -594,18 +688,23 @@ __device__ __forceinline__ void comp_tile(const float* __restrict__ mxp, const f
         const float4 a4 = *reinterpret_cast<const float4*>(lxp + k);
         const float4 b4 = *reinterpret_cast<const float4*>(lyp + k);
         const float4 c4 = *reinterpret_cast<const float4*>(lzp + k);
-        comp_pair(x4.x, y4.x, z4.x, a4.x, b4.x, c4.x, thx, thy, thz, tlx, tly, tlz, eps2, bx, by, bz);
-        comp_pair(x4.y, y4.y, z4.y, a4.y, b4.y, c4.y, thx, thy, thz, tlx, tly, tlz, eps2, bx, by, bz);
-        comp_pair(x4.z, y4.z, z4.z, a4.z, b4.z, c4.z, thx, thy, thz, tlx, tly, tlz, eps2, bx, by, bz);
-        comp_pair(x4.w, y4.w, z4.w, a4.w, b4.w, c4.w, thx, thy, thz, tlx, tly, tlz, eps2, bx, by, bz);
+        comp_pair(a, xl, src0 + k + 0, x4.x, y4.x, z4.x, a4.x, b4.x, c4.x, thx, thy, thz, tlx, tly, tlz, eps2,
+                  rc2, bx, by, bz);
+        comp_pair(a, xl, src0 + k + 1, x4.y, y4.y, z4.y, a4.y, b4.y, c4.y, thx, thy, thz, tlx, tly, tlz, eps2,
+                  rc2, bx, by, bz);
+        comp_pair(a, xl, src0 + k + 2, x4.z, y4.z, z4.z, a4.z, b4.z, c4.z, thx, thy, thz, tlx, tly, tlz, eps2,
+                  rc2, bx, by, bz);
+        comp_pair(a, xl, src0 + k + 3, x4.w, y4.w, z4.w, a4.w, b4.w, c4.w, thx, thy, thz, tlx, tly, tlz, eps2,
+                  rc2, bx, by, bz);
     }
     for (; k < cnt; ++k)
-        comp_pair(mxp[k], myp[k], mzp[k], lxp[k], lyp[k], lzp[k], thx, thy, thz, tlx, tly, tlz, eps2,
-                  bx, by, bz);
+        comp_pair(a, xl, src0 + k, mxp[k], myp[k], mzp[k], lxp[k], lyp[k], lzp[k], thx, thy, thz,
+                  tlx, tly, tlz, eps2, rc2, bx, by, bz);
 }
 
 template <bool CHECK>
-__device__ __forceinline__ void diff_tile(const float* __restrict__ mxp,
+__device__ __forceinline__ void diff_tile(const FieldArgs& a, ExactList& xl, uint32_t src0,
+                                          const float* __restrict__ mxp,
                                           const float* __restrict__ myp,
                                           const float* __restrict__ mzp,
                                           const float* __restrict__ lxp,
@@ -619,17 +718,17 @@ __device__ __forceinline__ void diff_tile(const float* __restrict__ mxp,
         const float4 x4 = *reinterpret_cast<const float4*>(mxp + k);
         const float4 y4 = *reinterpret_cast<const float4*>(myp + k);
         const float4 z4 = *reinterpret_cast<const float4*>(mzp + k);
-        diff_pair<CHECK>(lxp, lyp, lzp, k + 0, x4.x, y4.x, z4.x, thx, thy, thz, tlx, tly, tlz,
+        diff_pair<CHECK>(a, xl, src0 + k + 0, lxp, lyp, lzp, k + 0, x4.x, y4.x, z4.x, thx, thy, thz, tlx, tly, tlz,
                          eps2, rc2, bx, by, bz);
-        diff_pair<CHECK>(lxp, lyp, lzp, k + 1, x4.y, y4.y, z4.y, thx, thy, thz, tlx, tly, tlz,
+        diff_pair<CHECK>(a, xl, src0 + k + 1, lxp, lyp, lzp, k + 1, x4.y, y4.y, z4.y, thx, thy, thz, tlx, tly, tlz,
                          eps2, rc2, bx, by, bz);
-        diff_pair<CHECK>(lxp, lyp, lzp, k + 2, x4.z, y4.z, z4.z, thx, thy, thz, tlx, tly, tlz,
+        diff_pair<CHECK>(a, xl, src0 + k + 2, lxp, lyp, lzp, k + 2, x4.z, y4.z, z4.z, thx, thy, thz, tlx, tly, tlz,
                          eps2, rc2, bx, by, bz);
-        diff_pair<CHECK>(lxp, lyp, lzp, k + 3, x4.w, y4.w, z4.w, thx, thy, thz, tlx, tly, tlz,
+        diff_pair<CHECK>(a, xl, src0 + k + 3, lxp, lyp, lzp, k + 3, x4.w, y4.w, z4.w, thx, thy, thz, tlx, tly, tlz,
                          eps2, rc2, bx, by, bz);
     }
     for (; k < cnt; ++k)
-        diff_pair<CHECK>(lxp, lyp, lzp, k, mxp[k], myp[k], mzp[k], thx, thy, thz, tlx, tly, tlz,
+        diff_pair<CHECK>(a, xl, src0 + k, lxp, lyp, lzp, k, mxp[k], myp[k], mzp[k], thx, thy, thz, tlx, tly, tlz,
                          eps2, rc2, bx, by, bz);
 }
 
@@ -655,6 +754,7 @@ struct ExpandedLds {
     float sh[2][7][kTile];  // staged: -2 s_x, -2 s_y, -2 s_z, |s|^2 + eps^2, lo_x, lo_y, lo_z
     double box[6][kFieldThreads / 64];
     double tbox[2][6];      // bounding box of the staged source tile
+    ExactList xl;           // close pairs of the item
 };
 
 // COMP: tiles closer than rho/4 to the targets take the compensated
@@ -729,8 +829,9 @@ __device__ __forceinline__ void expanded_item(const FieldArgs& a, const FieldIte
     hi_z = uniform(hi_z);
     const double ox = 0.5 * (lo_x + hi_x), oy = 0.5 * (lo_y + hi_y), oz = 0.5 * (lo_z + hi_z);
     const double hx = 0.5 * (hi_x - lo_x), hy = 0.5 * (hi_y - lo_y), hz = 0.5 * (hi_z - lo_z);
-    const double rho2 = hx * hx + hy * hy + hz * hz;
-    const double rc2d = 0.0625 * rho2;  // (rho / 4)^2
+    // no expanded or unchecked tile may hold a pair closer than kExactRadius eps
+    const double rho2 = fmax(hx * hx + hy * hy + hz * hz, a.acc_box2);
+    const double rc2d = fmax(0.0625 * (hx * hx + hy * hy + hz * hz), a.acc_box2);  // (rho/4)^2
     const double eps2d = (double)a.eps2;
 
     float thx, thy, thz, tlx, tly, tlz, T;
@@ -747,8 +848,9 @@ __device__ __forceinline__ void expanded_item(const FieldArgs& a, const FieldIte
         T = (float)((double)thx * thx + (double)thy * thy + (double)thz * thz);
     }
     // this lane's close-pair radius squared: a quarter of its target's
-    // distance from the origin, as in field_tiles (0 for the padding lanes)
-    const float rc2 = 0.0625f * T;
+    // distance from the origin, as in field_tiles, and at least the exact-sum
+    // radius (0 for the padding lanes)
+    const float rc2 = ts < nt ? fmaxf(0.0625f * T, a.acc2) : 0.0f;
     float sw = 0.0f, sx = 0.0f, sy = 0.0f, sz = 0.0f;  // far tiles
     float ex = 0.0f, ey = 0.0f, ez = 0.0f;              // near tiles
 
@@ -820,14 +922,14 @@ __device__ __forceinline__ void expanded_item(const FieldArgs& a, const FieldIte
         } else {
             float bx = 0.0f, by = 0.0f, bz = 0.0f;
             if (g2 >= rc2d)
-                diff_tile<false>(mxp, myp, mzp, sh[buf][4], sh[buf][5], sh[buf][6], cnt, thx,
-                                 thy, thz, tlx, tly, tlz, a.eps2, rc2, bx, by, bz);
+                diff_tile<false>(a, L.xl, t * kTile, mxp, myp, mzp, sh[buf][4], sh[buf][5], sh[buf][6], cnt,
+                                 thx, thy, thz, tlx, tly, tlz, a.eps2, rc2, bx, by, bz);
             else if (COMP)
-                comp_tile(mxp, myp, mzp, sh[buf][4], sh[buf][5], sh[buf][6], cnt, thx, thy,
-                          thz, tlx, tly, tlz, a.eps2, bx, by, bz);
+                comp_tile(a, L.xl, t * kTile, mxp, myp, mzp, sh[buf][4], sh[buf][5], sh[buf][6], cnt, thx,
+                          thy, thz, tlx, tly, tlz, a.eps2, rc2, bx, by, bz);
             else
-                diff_tile<true>(mxp, myp, mzp, sh[buf][4], sh[buf][5], sh[buf][6], cnt, thx,
-                                thy, thz, tlx, tly, tlz, a.eps2, rc2, bx, by, bz);
+                diff_tile<true>(a, L.xl, t * kTile, mxp, myp, mzp, sh[buf][4], sh[buf][5], sh[buf][6], cnt,
+                                thx, thy, thz, tlx, tly, tlz, a.eps2, rc2, bx, by, bz);
             ex += bx;
             ey += by;
             ez += bz;
@@ -836,6 +938,7 @@ __device__ __forceinline__ void expanded_item(const FieldArgs& a, const FieldIte
         __syncthreads();
         buf ^= 1;
     }
+    exact_flush(a, L.xl, off, tbase);
 
     if (ts < nt) {
         // t sum w - sum s w, the second held as -2 sum s w
@@ -852,6 +955,7 @@ __device__ __forceinline__ void expanded_item(const FieldArgs& a, const FieldIte
 template <bool COMP>
 __global__ __launch_bounds__(kFieldThreads) void field_tiles_expanded(FieldArgs a) {
     __shared__ __align__(16) ExpandedLds L;
+    if (threadIdx.x == 0) L.xl.n = 0;  // ordered before any push by the item's first barrier
     expanded_item<COMP>(a, a.items[blockIdx.x], L);
 }
 
@@ -866,6 +970,7 @@ void field_queue_expanded(FieldArgs a) {
     __shared__ __align__(16) ExpandedLds L;
     __shared__ uint32_t next;
     const uint32_t n_items = *a.n_items;
+    if (threadIdx.x == 0) L.xl.n = 0;  // ordered before any push by the barriers below
     for (;;) {
         if (threadIdx.x == 0) next = atomicAdd(a.queue, 1u);
         __syncthreads();
@@ -1623,6 +1728,20 @@ __global__ __launch_bounds__(kStepThreads) void step_update(StepArgs a) {
                         sy += (double)pp[(size_t)(c * 3 + 1) * ps];
                         sz += (double)pp[(size_t)(c * 3 + 2) * ps];
                     }
+                    if (a.close) {
+                        // the exactly summed close pairs, cleared for the next launch
+                        unsigned long long* cp = a.close + slot;
+                        const long long cx = (long long)cp[0], cy = (long long)cp[ps],
+                                        cz = (long long)cp[2 * ps];
+                        if ((cx | cy | cz) != 0ll) {
+                            sx += (double)cx * a.close_unit;
+                            sy += (double)cy * a.close_unit;
+                            sz += (double)cz * a.close_unit;
+                            cp[0] = 0ull;
+                            cp[ps] = 0ull;
+                            cp[2 * ps] = 0ull;
+                        }
+                    }
                     ecx = a.K * sx;
                     ecy = a.K * sy;
                     ecz = a.K * sz;
@@ -1748,8 +1867,8 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
 // to the carrier each slot holds.
 __global__ void field_finish(const float* part, uint32_t pstride, const int32_t* ev_chunks,
                              int g0, int groups, const uint64_t* keys, const uint32_t* ev_off,
-                             KeyLayout kl, uint32_t n, double K, double* ex, double* ey,
-                             double* ez) {
+                             KeyLayout kl, uint32_t n, double K, unsigned long long* close,
+                             double close_unit, double* ex, double* ey, double* ez) {
     for (uint32_t slot = blockIdx.x * blockDim.x + threadIdx.x; slot < n;
          slot += gridDim.x * blockDim.x) {
         const uint64_t key = keys[slot];
@@ -1763,6 +1882,19 @@ __global__ void field_finish(const float* part, uint32_t pstride, const int32_t*
             sy += (double)part[(size_t)(c * 3 + 1) * pstride + slot];
             sz += (double)part[(size_t)(c * 3 + 2) * pstride + slot];
         }
+        if (close) {
+            unsigned long long* cp = close + slot;
+            const long long cx = (long long)cp[0], cy = (long long)cp[pstride],
+                            cz = (long long)cp[2 * (size_t)pstride];
+            if ((cx | cy | cz) != 0ll) {
+                sx += (double)cx * close_unit;
+                sy += (double)cy * close_unit;
+                sz += (double)cz * close_unit;
+                cp[0] = 0ull;
+                cp[pstride] = 0ull;
+                cp[2 * (size_t)pstride] = 0ull;
+            }
+        }
         ex[j] = K * sx;
         ey[j] = K * sy;
         ez[j] = K * sz;
@@ -1771,10 +1903,12 @@ __global__ void field_finish(const float* part, uint32_t pstride, const int32_t*
 
 hipError_t launch_field_finish(const float* part, uint32_t pstride, const int32_t* ev_chunks,
                                int g0, int groups, const uint64_t* keys, const uint32_t* ev_off,
-                               KeyLayout kl, uint32_t n, double K, double* ex, double* ey,
-                               double* ez, hipStream_t s) {
+                               KeyLayout kl, uint32_t n, double K, unsigned long long* close,
+                               double close_unit, double* ex, double* ey, double* ez,
+                               hipStream_t s) {
     field_finish<<<grid_for(n, 256, 8192), 256, 0, s>>>(part, pstride, ev_chunks, g0, groups, keys,
-                                                         ev_off, kl, n, K, ex, ey, ez);
+                                                         ev_off, kl, n, K, close, close_unit, ex,
+                                                         ey, ez);
     return hipGetLastError();
 }
 

@@ -1,0 +1,157 @@
+"""The Eq. (6) field in the middle and at the end of runs, against the FP64
+oracle on the same positions.
+
+After k steps the sorted carrier list has been rebuilt k times from moved
+holes, holes that reached the well are frozen in place and (by default) keep
+acting as sources from the collected segment of their event, and the step
+counter, the work items and the source split reflect the shrinking set of
+travelling holes.  gccd_field evaluates Eq. (6) on that state; these tests
+read the positions back and compare it with the oracle's field at exactly
+those positions, with the sources the paper's Fig. 2 loop keeps (every hole,
+or only the travelling ones when collected holes are not sources).  Both
+field criteria of test_gpu_parity.py are asserted.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+FIELD_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def g():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_11043_amd import gccd
+    return gccd
+
+
+@pytest.fixture(scope="module")
+def W():
+    from paper_2203_11043_amd import workloads
+    return workloads
+
+
+def gpu(*arrs):
+    return [torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda() for a in arrs]
+
+
+def errors(E, Eo, A):
+    d = np.linalg.norm(E - Eo, axis=0)
+    rms = math.sqrt(float(np.mean(np.sum(Eo**2, axis=0))))
+    return float(np.max(d / A)), float(np.max(d) / rms)
+
+
+def run_then_field(g, d, x, y, z, dt_ps, steps=None, until_active=None, offsets=None):
+    """Loads, runs `steps` steps (or in stretches of 8 steps until at most
+    `until_active` holes travel), then returns (positions, collect_step,
+    field, steps done, travelling holes)."""
+    ctx = g.gccd_init(g.Params.from_device(d))
+    try:
+        if offsets is None:
+            g.gccd_load(ctx, *gpu(x, y, z))
+        else:
+            g.gccd_load_events(ctx, offsets, *gpu(x, y, z))
+        done, na = 0, len(x)
+        if steps is not None:
+            done, na = g.gccd_run(ctx, dt_ps, steps)
+        else:
+            while na > until_active and done < 2000:
+                k, na = g.gccd_run(ctx, dt_ps, 8)
+                done += k
+        E = g.gccd_field(ctx, len(x)).cpu().numpy()
+        pos, cs = g.gccd_positions(ctx, len(x))
+        pos, cs = pos.cpu().numpy(), cs.cpu().numpy()
+    finally:
+        g.gccd_destroy(ctx)
+    return pos, cs, E, done, na
+
+
+def test_field_cloud_1e5_after_300_steps(g, W, orc):
+    """The benchmark's 1e5-hole cloud after 300 steps (the list re-sorted 300
+    times, the cloud expanded by repulsion and diffusion): 256 sampled holes
+    against all 1e5 sources."""
+    w = W.single_cloud(100000, seed=1)
+    d = dict(W.DEVICE)
+    pos, cs, E, done, na = run_then_field(g, d, w.x, w.y, w.z, w.dt_ps, steps=300)
+    assert done == 300
+    idx = np.random.default_rng(300).choice(w.n, 256, replace=False)
+    Eo, A = orc.field([pos[0, idx], pos[1, idx], pos[2, idx]], [pos[0], pos[1], pos[2]],
+                      with_magnitude=True)
+    ea, er = errors(E[:, idx], Eo, A)
+    print(f"[midrun] n=1e5 after 300 steps ({na} travelling): max|dE|/A = {ea:.3e}, "
+          f"max|dE|/rms|E| = {er:.3e}", flush=True)
+    assert ea <= FIELD_TOL and er <= FIELD_TOL
+
+
+def test_field_cloud_1e5_half_collected(g, W, orc):
+    """A 1e5-hole cloud 60 um deep run until about half of it is collected:
+    the frozen half keeps repelling from the collected segment.  128 sampled
+    travelling and 128 sampled collected holes against all 1e5 sources."""
+    w = W.single_cloud(100000, seed=2, depth_um=60.0)
+    d = dict(W.DEVICE)
+    pos, cs, E, done, na = run_then_field(g, d, w.x, w.y, w.z, w.dt_ps,
+                                          until_active=w.n // 2)
+    col = np.flatnonzero(cs >= 0)
+    trav = np.flatnonzero(cs < 0)
+    assert len(col) > w.n // 4 and len(trav) > w.n // 4
+    rng = np.random.default_rng(61)
+    idx = np.concatenate([rng.choice(trav, 128, replace=False), rng.choice(col, 128, replace=False)])
+    Eo, A = orc.field([pos[0, idx], pos[1, idx], pos[2, idx]], [pos[0], pos[1], pos[2]],
+                      with_magnitude=True)
+    ea, er = errors(E[:, idx], Eo, A)
+    print(f"[midrun] n=1e5 depth 60 um after {done} steps ({na} travelling): "
+          f"max|dE|/A = {ea:.3e}, max|dE|/rms|E| = {er:.3e}", flush=True)
+    assert ea <= FIELD_TOL and er <= FIELD_TOL
+
+
+@pytest.mark.parametrize("sources", [1, 0])
+def test_field_cloud_1e4_half_collected_every_hole(g, W, orc, sources):
+    """A shallow 1e4-hole cloud until about half is collected, every hole
+    judged; with collected_are_sources = 0 only the travelling holes are
+    sources (and the collected ones feel the travelling ones only)."""
+    w = W.single_cloud(10000, seed=3, depth_um=30.0)
+    d = dict(W.DEVICE, collected_are_sources=sources)
+    pos, cs, E, done, na = run_then_field(g, d, w.x, w.y, w.z, w.dt_ps,
+                                          until_active=w.n // 2)
+    trav = cs < 0
+    assert 0.25 * w.n < trav.sum() < 0.75 * w.n
+    src = pos if sources else pos[:, trav]
+    Eo, A = orc.field([pos[0], pos[1], pos[2]], [src[0], src[1], src[2]], with_magnitude=True)
+    ea, er = errors(E, Eo, A)
+    print(f"[midrun] n=1e4 depth 30 um, sources={'all' if sources else 'travelling'}, after "
+          f"{done} steps ({na} travelling): max|dE|/A = {ea:.3e}, max|dE|/rms|E| = {er:.3e}",
+          flush=True)
+    assert ea <= FIELD_TOL and er <= FIELD_TOL
+
+
+def test_field_batch_after_100_steps(g, W, orc):
+    """The 4096-cloud batch after 100 steps (the shallow clouds collected or
+    collecting, the deep ones expanded): 32 sampled events judged per event
+    against their own holes as sources."""
+    events = W.batch_of_clouds(4096, seed=1)
+    sizes = np.array([len(e[0]) for e in events])
+    off = np.concatenate([[0], np.cumsum(sizes)]).tolist()
+    x, y, z = (np.concatenate([e[k] for e in events]) for k in range(3))
+    d = dict(W.DEVICE)
+    pos, cs, E, done, na = run_then_field(g, d, x, y, z, 10.0, steps=100, offsets=off)
+    assert done == 100
+    pick = np.random.default_rng(100).choice(len(events), 32, replace=False)
+    worst_a = worst_r = 0.0
+    part_collected = 0
+    for e in pick:
+        sl = slice(off[e], off[e + 1])
+        p = pos[:, sl]
+        Eo, A = orc.field([p[0], p[1], p[2]], with_magnitude=True)
+        ea, er = errors(E[:, sl], Eo, A)
+        worst_a, worst_r = max(worst_a, ea), max(worst_r, er)
+        part_collected += int(0 < np.sum(cs[sl] >= 0) < sizes[e])
+    print(f"[midrun] batch after 100 steps ({na} travelling), 32 events "
+          f"({part_collected} partly collected): max|dE|/A = {worst_a:.3e}, "
+          f"max|dE|/rms|E| = {worst_r:.3e}", flush=True)
+    assert worst_a <= FIELD_TOL and worst_r <= FIELD_TOL

@@ -1,11 +1,13 @@
 """GPU (HIP, gfx950) path against the FP64 oracle, through the C ABI.
 
 Tolerances (derived from the arithmetic, see the design notes):
-  * Eq. (6) field: every carrier's error is at most 1e-5 of
-    A_j = K sum_i |r_ij| / (r_ij^2 + eps^2)^{3/2}, the sum of term magnitudes
-    (the scale that bounds the rounding error of any ordering of the sum;
-    the per-carrier relative error |dE|/|E| is ill-conditioned where the
-    terms cancel).  The normwise max |dE| / rms |E| is reported beside it.
+  * Eq. (6) field, two criteria, both asserted:
+      - normwise: max_j |dE_j| / rms_k |E_k| <= 1e-5 (the per-step field
+        criterion; the per-carrier relative error |dE|/|E| is ill-conditioned
+        where the terms cancel, at the centre of a cloud);
+      - per carrier: |dE_j| <= 1e-5 A_j, A_j = K sum_i |r_ij| /
+        (r_ij^2 + eps^2)^{3/2} the sum of term magnitudes (the scale that
+        bounds the rounding error of any ordering of the sum).
   * Coulomb-off runs: same Philox words on both sides, so positions agree to
     device-libm rounding (1e-10 um) and collection steps exactly.
   * Coulomb-on runs: trajectories drift apart through FP32 rounding, so cloud
@@ -87,7 +89,7 @@ def test_field_cloud_1000_all_targets(g, W, orc):
     Eo, A = orc.field([w.x, w.y, w.z], with_magnitude=True)
     ea, er = field_errors(E, Eo, A)
     report("cloud n=1000", ea, er)
-    assert ea <= FIELD_TOL
+    assert ea <= FIELD_TOL and er <= FIELD_TOL
 
 
 @pytest.mark.parametrize("tpt,chunks", [(1, 1), (2, 1), (4, 1), (1, 3), (2, 8), (4, 32), (1, 64), (0, 0)])
@@ -100,7 +102,7 @@ def test_field_ragged_launch_shapes(g, W, orc, tpt, chunks):
     Eo, A = orc.field([w.x, w.y, w.z], with_magnitude=True)
     ea, er = field_errors(E, Eo, A)
     report(f"cloud n=5003 tpt={st['targets_per_thread']} chunks={st['source_chunks']}", ea, er)
-    assert ea <= FIELD_TOL
+    assert ea <= FIELD_TOL and er <= FIELD_TOL
     if tpt:   # a fixed chunk count is capped at the event's 256-source tiles
         assert st["targets_per_thread"] == tpt
         assert st["source_chunks"] == min(chunks, (5003 + 255) // 256)
@@ -118,7 +120,7 @@ def test_field_full_size_sampled(g, W, orc, n):
     ea, er = field_errors(E[:, idx], Eo, A)
     report(f"cloud n={n} (256 sampled) tpt={st['targets_per_thread']} "
            f"chunks={st['source_chunks']}", ea, er)
-    assert ea <= FIELD_TOL
+    assert ea <= FIELD_TOL and er <= FIELD_TOL
 
 
 def test_field_muon_track_sampled(g, W, orc):
@@ -133,7 +135,7 @@ def test_field_muon_track_sampled(g, W, orc):
     Eo, A = orc.field([o.x[idx], o.y[idx], o.z[idx]], [o.x, o.y, o.z], with_magnitude=True)
     ea, er = field_errors(E[:, idx], Eo, A)
     report(f"track n={w.n} (256 sampled)", ea, er)
-    assert ea <= FIELD_TOL
+    assert ea <= FIELD_TOL and er <= FIELD_TOL
 
 
 def test_field_collected_not_sources(g, W, orc):
@@ -148,7 +150,7 @@ def test_field_collected_not_sources(g, W, orc):
     Eo, A = orc.field([w.x, w.y, w.z], src, with_magnitude=True)
     ea, er = field_errors(E[:, act], Eo[:, act], A[act])
     report("cloud n=3000, active sources only", ea, er)
-    assert ea <= FIELD_TOL
+    assert ea <= FIELD_TOL and er <= FIELD_TOL
 
 
 def test_field_far_from_origin_across_key_wrap(g, W, orc):
@@ -165,11 +167,11 @@ def test_field_far_from_origin_across_key_wrap(g, W, orc):
     Eo, A = orc.field([x, y, z], with_magnitude=True)
     ea, er = field_errors(E, Eo, A)
     report(f"cloud n={n} at x={cx:.1f} um, y={cy:.1f} um", ea, er)
-    assert ea <= FIELD_TOL
+    assert ea <= FIELD_TOL and er <= FIELD_TOL
     # the same holes near the origin: the same field to rounding
     E0, _ = gpu_field(g, p, x - cx + 480.0, y - cy + 480.0, z)
     Eo0, A0 = orc.field([x - cx + 480.0, y - cy + 480.0, z], with_magnitude=True)
-    assert field_errors(E0, Eo0, A0)[0] <= FIELD_TOL
+    assert max(field_errors(E0, Eo0, A0)) <= FIELD_TOL
     assert np.max(np.linalg.norm(E - E0, axis=0) / A) <= 2 * FIELD_TOL
 
 
@@ -184,7 +186,7 @@ def test_field_coincident_holes(g, W, orc):
     Eo, A = orc.field([x, y, z], with_magnitude=True)
     ea, er = field_errors(E, Eo, A)
     report(f"cloud n={3 * u}, each position held by 3 holes", ea, er)
-    assert ea <= FIELD_TOL
+    assert ea <= FIELD_TOL and er <= FIELD_TOL
     for k in (1, 2):
         assert np.max(np.linalg.norm(E[:, k * u:(k + 1) * u] - E[:, :u], axis=0)
                       / A[:u]) <= 2 * FIELD_TOL
@@ -203,7 +205,7 @@ def test_field_two_distant_clusters(g, W, orc):
     Eo, A = orc.field([x, y, z], with_magnitude=True)
     ea, er = field_errors(E, Eo, A)
     report(f"two clusters of {n}, 150 um apart", ea, er)
-    assert ea <= FIELD_TOL
+    assert ea <= FIELD_TOL and er <= FIELD_TOL
     # each cluster's own field sums to zero; the other one, 150 um away, pushes
     # the lower cluster down and the upper one up, as a point charge would
     point = orc.coulomb_constant(d["eps_r"]) * n / 150.0**2
