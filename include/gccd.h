@@ -321,6 +321,27 @@ int gccd_set_closure(gccd_ctx* c, const float* weights, int64_t n_weights,
 int gccd_closure_parts(gccd_ctx* c, double* near_x, double* near_y, double* near_z,
                        double* far_x, double* far_y, double* far_z, float* rho, double* grid);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.
+ *
+ * The Eq. (6) field of n holes of one event, as gccd_init(p) + gccd_load(n,
+ * x, y, z) + gccd_field + gccd_destroy return it in the default launch shape
+ * and precision (the same kernels, work items and summation order: the same
+ * values bit for bit), without allocating: every intermediate buffer lives in
+ * one static device array of about 29 MB, which each GPU the library runs on
+ * holds until the process ends.  x, y, z are device arrays of n FP64
+ * positions in um (read only: the load-time mirror and collection are applied
+ * to internal copies); ex, ey, ez device arrays of n FP64 values in V/cm,
+ * carrier order.  Asynchronous on hip_stream (NULL: the null stream); no
+ * host synchronisation, no memory-set commands.  Every call on a GPU uses
+ * that GPU's one array: calls that overlap on one GPU (other streams, other
+ * threads) race and must be serialised by the caller.  GCCD_E_INVALID for
+ * invalid parameters (as gccd_init), n < 1, n > GCCD_NOALLOC_MAX_CARRIERS or
+ * NULL pointers; GCCD_E_DEVICE when a launch or copy fails. */
+#define GCCD_NOALLOC_MAX_CARRIERS 32768
+int gccd_field_noalloc(const gccd_params* p, int64_t n, const double* x, const double* y,
+                       const double* z, double* ex, double* ey, double* ez, void* hip_stream);
+
 /* on = 1 times every Eq. (6) launch with HIP events on the context's stream
  * (reported by gccd_stats); on = 0 stops timing. */
 int gccd_set_timing(gccd_ctx* c, int32_t on);

@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <cmath>
 #include <new>
 #include <numeric>
@@ -1507,6 +1508,184 @@ int gccd_stats(gccd_ctx* c, gccd_stats_t* out) {
     out->max_source_chunks = c->max_chunks;
     out->closure_steps = c->closure_steps;
     out->near_chunks = c->near_chunks;
+    return GCCD_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// gccd_field_noalloc: gccd_init + gccd_load + gccd_field + gccd_destroy of one
+// event in the default launch shape and precision, on buffers carved from a
+// static device array instead of allocated ones.
+// ---------------------------------------------------------------------------
+namespace {
+
+// Regions of the scratch array, in bytes, for at most GCCD_NOALLOC_MAX_CARRIERS
+// holes (each 256-byte aligned).
+constexpr size_t kNaN = GCCD_NOALLOC_MAX_CARRIERS;
+constexpr size_t kNaTiles = (kNaN + kTile - 1) / kTile;
+constexpr size_t kNaBlocks = (kNaN + kFieldThreads - 1) / kFieldThreads;
+constexpr size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+constexpr size_t kNaPos = align256(kNaN * sizeof(double));        // x, y, z, px, py, pz
+constexpr size_t kNaI32 = align256(kNaN * sizeof(uint32_t));      // cstep, ev_of
+constexpr size_t kNaKeys = align256(kNaN * sizeof(uint64_t));     // keys[0], keys[1]
+constexpr size_t kNaClose = align256(3 * kNaN * sizeof(unsigned long long));
+constexpr size_t kNaPart = align256((size_t)kMaxChunks * 3 * kNaN * sizeof(float));
+constexpr size_t kNaBox = align256((size_t)kBoxRows * kNaTiles * sizeof(double));
+constexpr size_t kNaItems = align256(kNaBlocks * kMaxChunks * sizeof(FieldItem));
+constexpr size_t kNaSmall = align256((8 + kNaTiles + kMetaWords + kSchedWords) * sizeof(uint32_t));
+constexpr size_t kNaBytes =
+    6 * kNaPos + 2 * kNaI32 + 2 * kNaKeys + kNaClose + kNaPart + kNaBox + kNaItems + kNaSmall;
+
+__device__ __align__(256) unsigned char scratch[kNaBytes];
+
+// Per device: the address of that device's copy of `scratch` (host code may
+// not use the array's name as a device address) and the launch facts the
+// chunk choice depends on.
+constexpr int kNaDevices = 64;
+struct NoAllocDevice {
+    unsigned char* ptr = nullptr;
+    int n_cu = 0;
+    int slots = 0;  // workgroups of the default Eq. (6) kernel per compute unit
+};
+std::mutex g_na_mutex;
+NoAllocDevice g_na[kNaDevices];
+
+int noalloc_device(int dev, NoAllocDevice* out) {
+    if (dev < 0 || dev >= kNaDevices) return GCCD_E_DEVICE;
+    std::lock_guard<std::mutex> lock(g_na_mutex);
+    NoAllocDevice& d = g_na[dev];
+    if (!d.ptr) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return GCCD_E_DEVICE;
+        }
+        int n_cu = 0;
+        if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) !=
+                hipSuccess ||
+            n_cu <= 0)
+            n_cu = 256;
+        d.n_cu = n_cu;
+        d.slots = field_slots_per_cu(1, GCCD_PRECISION_DEFAULT);
+        d.ptr = static_cast<unsigned char*>(p);
+    }
+    *out = d;
+    return GCCD_OK;
+}
+
+}  // namespace
+
+int gccd_field_noalloc(const gccd_params* p, int64_t n, const double* x, const double* y,
+                       const double* z, double* ex, double* ey, double* ez, void* hip_stream) {
+    if (validate(p) != GCCD_OK || n < 1 || n > GCCD_NOALLOC_MAX_CARRIERS || !x || !y || !z ||
+        !ex || !ey || !ez)
+        return GCCD_E_INVALID;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return GCCD_E_DEVICE;
+    NoAllocDevice d;
+    if (int r = noalloc_device(dev, &d); r != GCCD_OK) return r;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const uint32_t nn = (uint32_t)n;
+
+    // the chunk plan of choose_chunks for one event, one target per thread
+    const uint64_t tiles = ((uint64_t)nn + kTile - 1) / kTile;
+    const uint64_t blocks = ((uint64_t)nn + kFieldThreads - 1) / kFieldThreads;
+    const uint64_t cap = kMaxChunks;
+    int32_t g = (int32_t)std::min<uint64_t>(auto_chunks(nn, blocks, d.n_cu, cap), cap);
+    int32_t tail = 0;
+    uint32_t split = 0;
+    {
+        const uint64_t slots = (uint64_t)d.n_cu * (uint64_t)d.slots;
+        const uint64_t big = (tiles + g - 1) / (uint64_t)g;
+        if (blocks * (uint64_t)g < 32 * slots && big >= 4)
+            (void)event_tail(tiles, blocks, (uint64_t)g, cap, (int64_t)(slots * big / 2), &g,
+                             &tail, &split);
+    }
+    const uint32_t n_items = (uint32_t)(blocks * (uint64_t)g);
+
+    // carve the regions
+    unsigned char* q = d.ptr;
+    auto take = [&](size_t bytes) {
+        unsigned char* r = q;
+        q += bytes;
+        return r;
+    };
+    double* cx = reinterpret_cast<double*>(take(kNaPos));
+    double* cy = reinterpret_cast<double*>(take(kNaPos));
+    double* cz = reinterpret_cast<double*>(take(kNaPos));
+    double* px = reinterpret_cast<double*>(take(kNaPos));
+    double* py = reinterpret_cast<double*>(take(kNaPos));
+    double* pz = reinterpret_cast<double*>(take(kNaPos));
+    int32_t* cstep = reinterpret_cast<int32_t*>(take(kNaI32));
+    uint32_t* ev_of = reinterpret_cast<uint32_t*>(take(kNaI32));
+    uint64_t* keys0 = reinterpret_cast<uint64_t*>(take(kNaKeys));
+    uint64_t* keys1 = reinterpret_cast<uint64_t*>(take(kNaKeys));
+    unsigned long long* close = reinterpret_cast<unsigned long long*>(take(kNaClose));
+    float* part = reinterpret_cast<float*>(take(kNaPart));
+    double* box = reinterpret_cast<double*>(take(kNaBox));
+    FieldItem* items = reinterpret_cast<FieldItem*>(take(kNaItems));
+    uint32_t* small = reinterpret_cast<uint32_t*>(take(kNaSmall));
+    uint32_t* ev_off = small;          // [2]
+    uint32_t* ev_tile = small + 2;     // [2]
+    uint32_t* ev_active = small + 4;   // [1]
+    int32_t* ev_chunks = reinterpret_cast<int32_t*>(small + 5);  // [1]
+    uint32_t* meta = small + 8;        // [kMetaWords]
+    uint32_t* sched = meta + kMetaWords;
+    uint32_t* tile_event = sched + kSchedWords;  // [tiles]
+
+    const KeyLayout kl{std::max<uint32_t>(1, bits_for((uint64_t)nn)), 0u};
+    const size_t dbytes = (size_t)nn * sizeof(double);
+#define NA_HIP(call)                                   \
+    do {                                               \
+        if ((call) != hipSuccess) {                    \
+            (void)hipGetLastError();                   \
+            return GCCD_E_DEVICE;                      \
+        }                                              \
+    } while (0)
+    // meta and sched are contiguous: both zeroed
+    NA_HIP(launch_noalloc_setup(nn, (uint32_t)tiles, g, tail, split, (uint32_t)blocks, ev_off,
+                                ev_tile, ev_chunks, tile_event, meta, kMetaWords + kSchedWords,
+                                items, close, st));
+    NA_HIP(hipMemcpyAsync(cx, x, dbytes, hipMemcpyDeviceToDevice, st));
+    NA_HIP(hipMemcpyAsync(cy, y, dbytes, hipMemcpyDeviceToDevice, st));
+    NA_HIP(hipMemcpyAsync(cz, z, dbytes, hipMemcpyDeviceToDevice, st));
+    NA_HIP(launch_load(cz, cstep, ev_off, ev_of, 1u, nn, p->thickness_um, p->well_z_um,
+                       meta + kMetaCount, st));
+    NA_HIP(launch_make_keys(cx, cy, cz, cstep, ev_of, ev_off, nn, kl, keys1, st));
+    NA_HIP(sort_keys(keys1, keys0, nn, st));
+    NA_HIP(launch_count(keys0, ev_off, 1u, kl, p->collected_are_sources, ev_active,
+                        reinterpret_cast<unsigned long long*>(meta + kMetaPending), st));
+    NA_HIP(launch_gather(keys0, ev_off, ev_tile, tile_event, ev_active, p->collected_are_sources,
+                         (uint32_t)tiles, kl, cx, cy, cz, px, py, pz, box, (uint32_t)tiles, st));
+    FieldArgs fa{};
+    fa.items = items;
+    fa.ev_off = ev_off;
+    fa.ev_active = ev_active;
+    fa.ev_tile = ev_tile;
+    fa.targets_all = 1;
+    fa.sources_all = p->collected_are_sources;
+    fa.px = px;
+    fa.py = py;
+    fa.pz = pz;
+    fa.tile_box = box;
+    fa.tile_stride = (uint32_t)tiles;
+    const double eps2 = p->softening_um * p->softening_um;
+    fa.eps2 = (float)eps2;
+    fa.eps2d = eps2;
+    fa.part = part;
+    fa.pstride = nn;
+    fa.n_items = sched + kSchedItems;
+    fa.queue = sched + kSchedQueue;
+    fa.near_compensated = n_items <= (uint64_t)d.n_cu * (uint64_t)d.slots ? 1 : 0;
+    fa.acc2 = (float)((kExactRadius * kExactRadius + 1.0) * eps2);
+    fa.acc_box2 = kExactRadius * kExactRadius * eps2;
+    fa.acc_scale = std::ldexp(eps2, kExactShift);
+    fa.close = close;
+    NA_HIP(launch_field(fa, 1, GCCD_PRECISION_DEFAULT, n_items, 0u, st));
+    const double K = kQ / (4.0 * kPi * kEps0 * p->eps_r) * 1e12 * 1e-2;
+    NA_HIP(launch_field_finish(part, nn, ev_chunks, 0, 0, keys0, ev_off, kl, nn, K, close,
+                               std::ldexp(1.0 / eps2, -kExactShift), ex, ey, ez, st));
+#undef NA_HIP
     return GCCD_OK;
 }
 

@@ -161,6 +161,12 @@ hipError_t launch_field_finish(const float* part, uint32_t pstride, const int32_
                                KeyLayout kl, uint32_t n, double K, unsigned long long* close,
                                double close_unit, double* ex, double* ey, double* ez,
                                hipStream_t s);
+// gccd_field_noalloc: event tables, zeroed words and close sums, work items.
+hipError_t launch_noalloc_setup(uint32_t n, uint32_t tiles, int32_t g, int32_t tail,
+                                uint32_t split, uint32_t blocks, uint32_t* ev_off,
+                                uint32_t* ev_tile, int32_t* ev_chunks, uint32_t* tile_event,
+                                uint32_t* words, uint32_t n_words, FieldItem* items,
+                                unsigned long long* close, hipStream_t s);
 hipError_t launch_image(const double* x, const double* y, const int32_t* cstep,
                         const uint32_t* ev_of, uint32_t n, int per_event, double x0, double y0,
                         double pitch, int32_t nx, int32_t ny, uint32_t* counts,

@@ -1912,6 +1912,65 @@ hipError_t launch_field_finish(const float* part, uint32_t pstride, const int32_
     return hipGetLastError();
 }
 
+// The per-call state of gccd_field_noalloc (one event of n holes, t tiles,
+// `blocks` target blocks, g chunks of which the last `tail` form the tail
+// layer from tile `split`), written in its scratch memory: event tables,
+// zeroed counters and close-pair sums, and the work items in the order the
+// context's item builder lists them for one event.
+__global__ void noalloc_setup(uint32_t n, uint32_t tiles, int32_t g, int32_t tail, uint32_t split,
+                              uint32_t blocks, uint32_t* ev_off, uint32_t* ev_tile,
+                              int32_t* ev_chunks, uint32_t* tile_event, uint32_t* words,
+                              uint32_t n_words, FieldItem* items, unsigned long long* close) {
+    const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    if (i0 == 0) {
+        ev_off[0] = 0u;
+        ev_off[1] = n;
+        ev_tile[0] = 0u;
+        ev_tile[1] = tiles;
+        ev_chunks[0] = g;
+    }
+    for (uint64_t i = i0; i < n_words; i += stride) words[i] = 0u;
+    for (uint64_t i = i0; i < tiles; i += stride) tile_event[i] = 0u;
+    for (uint64_t i = i0; i < 3ull * n; i += stride) close[i] = 0ull;
+    const uint32_t s1 = (uint32_t)(g - tail), s2 = (uint32_t)tail;
+    const uint64_t first = (uint64_t)blocks * s1, total = first + (uint64_t)blocks * s2;
+    for (uint64_t k = i0; k < total; k += stride) {
+        FieldItem it;
+        it.event = 0u;
+        it.groups = (uint32_t)g;
+        it.pad = 0u;
+        if (k < first) {
+            const uint32_t b = (uint32_t)(k / s1), q = (uint32_t)((k % s1 + b) % s1);
+            it.blk = b;
+            it.group = q;
+            it.first = q;
+            it.end = s2 ? split : kTilesToEnd;
+            it.step = s1;
+        } else {
+            const uint64_t kk = k - first;
+            const uint32_t b = (uint32_t)(kk / s2), q = (uint32_t)((kk % s2 + b) % s2);
+            it.blk = b;
+            it.group = s1 + q;
+            it.first = split + q;
+            it.end = kTilesToEnd;
+            it.step = s2;
+        }
+        items[k] = it;
+    }
+}
+
+hipError_t launch_noalloc_setup(uint32_t n, uint32_t tiles, int32_t g, int32_t tail,
+                                uint32_t split, uint32_t blocks, uint32_t* ev_off,
+                                uint32_t* ev_tile, int32_t* ev_chunks, uint32_t* tile_event,
+                                uint32_t* words, uint32_t n_words, FieldItem* items,
+                                unsigned long long* close, hipStream_t s) {
+    noalloc_setup<<<grid_for(3ull * n, 256, 1024), 256, 0, s>>>(
+        n, tiles, g, tail, split, blocks, ev_off, ev_tile, ev_chunks, tile_event, words, n_words,
+        items, close);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Sec. V.A image: half-open pixels, index floor((x - x0) / pitch) in IEEE
 // FP64 (correctly rounded division), integer atomics into the caller's grid:

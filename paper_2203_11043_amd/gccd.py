@@ -18,6 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("GCCD_LIB") or os.path.join(_HERE, "libgccd.so")
 ABI_VERSION = 3
 CLOSURE_WEIGHTS = 290784      # GCCD_CLOSURE_WEIGHTS
+GCCD_NOALLOC_MAX_CARRIERS = 32768   # largest load of gccd_field_noalloc
 
 GCCD_OK = 0
 GCCD_E_INVALID = -1
@@ -41,8 +42,8 @@ SCHEDULES = {"grid": 0, "queue": 1, "graph": 2}   # GCCD_SCHEDULE_*
 EXPORTS = ("gccd_init", "gccd_load", "gccd_load_events", "gccd_run", "gccd_image",
            "gccd_image_events", "gccd_field", "gccd_positions", "gccd_stats",
            "gccd_set_launch", "gccd_autotune", "gccd_set_precision", "gccd_set_closure",
-           "gccd_closure_parts", "gccd_set_timing", "gccd_set_schedule", "gccd_strerror",
-           "gccd_last_error", "gccd_destroy")
+           "gccd_closure_parts", "gccd_set_timing", "gccd_set_schedule", "gccd_field_noalloc",
+           "gccd_strerror", "gccd_last_error", "gccd_destroy")
 
 
 class CParams(ctypes.Structure):
@@ -110,6 +111,7 @@ def _load():
     L.gccd_closure_parts.argtypes = [P, P, P, P, P, P, P, P, P]
     L.gccd_set_timing.argtypes = [P, i32]
     L.gccd_set_schedule.argtypes = [P, i32]
+    L.gccd_field_noalloc.argtypes = [ctypes.POINTER(CParams), i64, P, P, P, P, P, P, P]
     L.gccd_strerror.argtypes = [ctypes.c_int]
     L.gccd_strerror.restype = ctypes.c_char_p
     L.gccd_last_error.argtypes = [P]
@@ -247,6 +249,24 @@ def gccd_field(ctx: int, n: int, out=None):
         out = torch.empty((3, n), dtype=torch.float64,
                           device=torch.device("cuda", torch.cuda.current_device()))
     _check(ctx, lib.gccd_field(ctx, out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr()))
+    return out
+
+
+def gccd_field_noalloc(params, x: torch.Tensor, y: torch.Tensor, z: torch.Tensor, out=None,
+                       stream=None):
+    """Eq. (6) at n holes of one event without any device allocation by the
+    library; returns a (3, n) float64 device tensor (V/cm).  `out` (3, n)
+    float64 on the device may be given so that the call allocates nothing."""
+    n = int(x.numel())
+    cp = params.c() if isinstance(params, Params) else params
+    if out is None:
+        out = torch.empty((3, n), dtype=torch.float64, device=x.device)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    st = stream.cuda_stream
+    _check(None, lib.gccd_field_noalloc(ctypes.byref(cp), n, _f64_dev(x, n), _f64_dev(y, n),
+                                        _f64_dev(z, n), out[0].data_ptr(), out[1].data_ptr(),
+                                        out[2].data_ptr(), st))
     return out
 
 

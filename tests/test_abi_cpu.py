@@ -29,7 +29,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported(g):
     names = declared_functions()
-    assert len(names) == 19
+    assert len(names) == 20
     for name in names:
         assert hasattr(g.lib, name), name
     assert sorted(g.EXPORTS) == names
@@ -48,6 +48,7 @@ def test_struct_layout_matches_header(g, tmp_path):
         " offsetof(gccd_stats_t, source_chunks), offsetof(gccd_stats_t, max_source_chunks),"
         " offsetof(gccd_stats_t, near_chunks), offsetof(gccd_stats_t, graph_replays),"
         " offsetof(gccd_stats_t, graph_usable), GCCD_CLOSURE_WEIGHTS);"
+        'printf("%d\\n", GCCD_NOALLOC_MAX_CARRIERS);'
         "\nreturn 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o",
@@ -57,7 +58,7 @@ def test_struct_layout_matches_header(g, tmp_path):
     want = [ctypes.sizeof(P), P.thickness_um.offset, P.coulomb.offset, P.seed.offset,
             P.event.offset, ctypes.sizeof(S), S.field_ms.offset, S.source_chunks.offset,
             S.max_source_chunks.offset, S.near_chunks.offset, S.graph_replays.offset,
-            S.graph_usable.offset, g.CLOSURE_WEIGHTS]
+            S.graph_usable.offset, g.CLOSURE_WEIGHTS, g.GCCD_NOALLOC_MAX_CARRIERS]
     assert list(map(int, out)) == want
 
 
