@@ -154,6 +154,52 @@ def closure_leg(gccd, workloads, torch, n: int = 1000000, seed: int = 2000,
     return out
 
 
+DRIFT_BYTES_PER_CARRIER_STEP = 60   # x, y, z read and written (48), collection step (8), event (4)
+
+
+def drift_leg(gccd, workloads, torch, n: int, steps: int, warm: int, cpu: bool) -> dict:
+    """The paper's O(N) case (Sec. IV, Coulomb off): n holes drift and
+    diffuse (Eqs. (1)-(4)), one step_update launch per time step.  A wide
+    cloud 400 um deep, so that no hole is collected in the timed steps.  The
+    oracle leg times whole Coulomb-off steps of the first 1e6 of the holes."""
+    import numpy as np
+    x, y, z = workloads.gaussian_cloud(n, 20.0, (480.0, 480.0, 400.0), 1, stream=30)
+    d = dict(workloads.DEVICE, coulomb=0)
+    xs = [torch.as_tensor(v).cuda() for v in (x, y, z)]
+    ctx = gccd.gccd_init(gccd.Params.from_device(d))
+    try:
+        gccd.gccd_load(ctx, *xs)
+        gccd.gccd_run(ctx, workloads.DT_PS, warm)
+        torch.cuda.synchronize()
+        s0 = gccd.gccd_stats(ctx)
+        t0 = time.perf_counter()
+        done, na = gccd.gccd_run(ctx, workloads.DT_PS, steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        s1 = gccd.gccd_stats(ctx)
+    finally:
+        gccd.gccd_destroy(ctx)
+    cs = s1["carrier_steps"] - s0["carrier_steps"]
+    rate = cs / dt
+    out = {"n": n, "steps": done, "travelling": na, "ms_per_step": dt / max(done, 1) * 1e3,
+           "carrier_steps_per_s": rate,
+           "roofline": {"bound": "hbm", "achieved": rate * DRIFT_BYTES_PER_CARRIER_STEP / 1e9,
+                        "peak": 8000.0, "unit": "GB/s",
+                        "frac": rate * DRIFT_BYTES_PER_CARRIER_STEP / 8e12,
+                        "bytes_per_carrier_step": DRIFT_BYTES_PER_CARRIER_STEP}}
+    if cpu:
+        import oracle
+        m = min(n, 1000000)
+        st = oracle.State(oracle.Device(**d), x[:m], y[:m], z[:m])
+        t0 = time.perf_counter()
+        st.run(workloads.DT_PS, 2)
+        t = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 2 * m / t, "unit": "carrier-steps/s",
+                               "cores": oracle.num_threads(), "kind": "oracle",
+                               "sample": f"two Coulomb-off steps of {m} holes, FP64, {t:.1f} s"}
+    return out
+
+
 def sweep(gccd, workloads, torch, cpu: bool) -> dict:
     """The paper's timing protocol (Sec. IV, Fig. 4): 10 time steps of one
     cloud at each N, Coulomb on and off, on the GPU (median of 3 after one
@@ -225,12 +271,14 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", choices=("cloud", "batch", "closure", "sweep"), default="cloud",
+    ap.add_argument("--workload", choices=("cloud", "batch", "closure", "sweep", "drift"),
+                    default="cloud",
                     help="cloud: one 1e5-hole cloud (default); batch: 4096 clouds of "
                          "200-20000 holes in one launch; closure: only the closure-versus-"
                          "exact leg on the 1e6-hole cloud (--steps closure steps); sweep: the "
-                         "paper's 10-step timing over N, Coulomb on and off, and whole runs")
-    ap.add_argument("--n", type=int, default=100000)
+                         "paper's 10-step timing over N, Coulomb on and off, and whole runs; "
+                         "drift: the Coulomb-off O(N) step on --n holes (2^24 by default)")
+    ap.add_argument("--n", type=int, default=0, help="holes (0: 1e5, or 2^24 for drift)")
     ap.add_argument("--events", type=int, default=4096)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--tpt", type=int, default=0, help="targets per thread (0 = auto)")
@@ -273,6 +321,20 @@ def main() -> int:
                                                         "cloud, a 1e4 cloud and the muon track"},
             "sweep": res}), flush=True)
         return 0
+    if args.workload == "drift":
+        res = drift_leg(gccd, workloads, torch, args.n or (1 << 24), args.steps, args.warmup,
+                        cpu=not args.no_cpu_baseline)
+        print(json.dumps({
+            "metric": "carrier-steps/s of the Coulomb-off step at 1 GPU",
+            "value": res["carrier_steps_per_s"], "unit": "carrier-steps/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["ms_per_step"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": f"{res['n']} holes, Gaussian of 20 um at depth 400 um, "
+                                   "Coulomb off (drift, mobility, diffusion, update)"},
+            "roofline": res["roofline"], "cpu_baseline": res.get("cpu_baseline"),
+            "drift": res}), flush=True)
+        return 0
     if args.workload == "closure":
         res = closure_leg(gccd, workloads, torch, closure_steps=args.steps, exact_steps=2)
         if res is None:
@@ -294,7 +356,7 @@ def main() -> int:
         w = workloads.Workload(f"batch_{args.events}", *(np.concatenate([e[k] for e in events])
                                                         for k in range(3)))
     else:
-        w = workloads.single_cloud(args.n, seed=args.seed)
+        w = workloads.single_cloud(args.n or 100000, seed=args.seed)
     if args.copy_calibration_mib:
         a = torch.empty(args.copy_calibration_mib * (1 << 20) // 4, dtype=torch.float32,
                         device="cuda").fill_(1.0)

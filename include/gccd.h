@@ -258,8 +258,8 @@ int gccd_set_precision(gccd_ctx* c, int32_t mode);
  *          place between replays, so one capture serves the whole run
  * QUEUE and GRAPH apply to one target per thread in the default precision;
  * other shapes use GRID.  A capture that fails, or that would hold a
- * memory-set node (the radix sort of a large load issues them), is dropped:
- * that load's steps are then issued one by one.  Every schedule runs the
+ * memory-set node (the library's own steps issue none), is dropped: that
+ * load's steps are then issued one by one.  Every schedule runs the
  * same kernels on the same items, so results are bit-identical.  Per-launch
  * timing (gccd_set_timing) needs events around each field launch, which
  * graph replays do not provide: with timing on, GRAPH issues its steps one

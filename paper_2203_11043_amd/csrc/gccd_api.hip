@@ -1297,7 +1297,7 @@ int gccd_run(gccd_ctx* c, double dt_ps, int64_t max_steps, int64_t* steps_done,
     sa.thickness = c->p.thickness_um;
     sa.z_well = c->p.well_z_um;
     sa.mu0 = c->mu0;
-    sa.ec = c->ec;
+    sa.log_ec = std::log(c->ec);
     sa.beta = c->beta;
     sa.inv_beta = c->inv_beta;
     sa.dt_s = dt_ps * 1e-12;

@@ -83,7 +83,7 @@ struct FieldArgs {
 // Pairs closer than kExactRadius softening lengths are summed exactly (see
 // FieldArgs::close); the fixed-point unit is 2^-kExactShift / eps^2, so the
 // largest term of Eq. (6), 0.385 / eps^2, takes 2^38.6 units.
-constexpr double kExactRadius = 32.0;
+constexpr double kExactRadius = 64.0;
 constexpr int kExactShift = 40;
 
 // Everything the per-carrier update of one step needs.
@@ -109,7 +109,7 @@ struct StepArgs {
     double K;                 // V um^2 / cm
     double a1, a2;            // Eq. (1)
     double thickness, z_well;
-    double mu0, ec, beta, inv_beta;   // Eq. (2) at the context's T
+    double mu0, log_ec, beta, inv_beta;   // Eq. (2) at the context's T (log_ec = log Ec)
     double dt_s;              // time step, s
     double vt;                // k_B T / q, V
     uint32_t step;             // the step index, or its offset from *step_base

@@ -201,7 +201,7 @@ __device__ __forceinline__ void exact_flush(const FieldArgs& a, ExactList& L, ui
 // Each tile's contributions are summed separately and then added to the
 // running sum (blocked summation).
 //
-// Pairs closer than kExactRadius eps (32 nm at eps = 1 nm) are the one case
+// Pairs closer than kExactRadius eps (64 nm at eps = 1 nm) are the one case
 // where that relative bound is not enough: their terms reach 0.385 / eps^2,
 // tens to hundreds of times the rms field of a cloud, and an FP32 term and the
 // FP32 additions that follow it would carry about 10u of that into the
@@ -585,8 +585,10 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles(FieldArgs a) {
 
 // Default precision, one target per lane: the far tiles in the expanded form.
 //
-// For a source tile whose bounding box lies more than rho from the targets'
-// box, every pair has |d| > rho, and the pair sum is taken from
+// For a source tile whose bounding box lies more than rho from the box of
+// the wave's targets (rho: the half-diagonal of the workgroup's targets, whose
+// centre is the origin), every pair has |d| > rho, and the pair sum is taken
+// from
 //     |d|^2 + eps^2 = (|s|^2 + eps^2) + |t|^2 - 2 t.s,
 //     sum d w = t sum w - sum s w,          w = (|d|^2 + eps^2)^{-3/2},
 // with s and t the hi parts relative to the workgroup origin.  The staged
@@ -601,11 +603,13 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles(FieldArgs a) {
 // scales the FP32 summation error of those tiles by that factor.  It is
 // formed in FP64 from the FP32 sums.
 //
-// Tiles within rho of the targets' box take the difference form exactly as
+// Tiles within rho of the wave's box take the difference form exactly as
 // field_tiles<1, DEFAULT> does (the sources' hi parts recovered from -2 s by
 // an exact halving inside the FMA), with the same close-pair rule (tiles
-// within rho/4 of the targets' box checked pair by pair against a quarter of
-// each target's distance from the origin), so in a launch that fills the GPU
+// within rho/4 of the wave's box checked pair by pair against a quarter of
+// each target's distance from the origin; a tile farther than that holds no
+// close pair of the wave, so the unchecked sum is the same), so in a launch
+// that fills the GPU
 // the close pairs -- and whole small events, which have no far tiles -- are
 // summed bit for bit as by that kernel.  Small loads differ on purpose: see
 // COMP below.
@@ -803,6 +807,11 @@ __device__ __forceinline__ void expanded_item(const FieldArgs& a, const FieldIte
     hi_x = wave_max(hi_x);
     hi_y = wave_max(hi_y);
     hi_z = wave_max(hi_z);
+    // this wave's own 64 targets: each wave classifies the source tiles by
+    // their distance from its own box (at least their distance from the
+    // workgroup's), so a tile near only the other waves' targets is far here
+    const double wl_x = uniform(lo_x), wl_y = uniform(lo_y), wl_z = uniform(lo_z);
+    const double wh_x = uniform(hi_x), wh_y = uniform(hi_y), wh_z = uniform(hi_z);
     if (lane == 0) {
         box[0][wave] = lo_x;
         box[1][wave] = lo_y;
@@ -895,10 +904,10 @@ __device__ __forceinline__ void expanded_item(const FieldArgs& a, const FieldIte
         const float* myp = sh[buf][1];
         const float* mzp = sh[buf][2];
         const double* tb = tbox[buf];
-        const double gx = fmax(0.0, fmax(tb[0] - hi_x, lo_x - tb[3]));
-        const double gy = fmax(0.0, fmax(tb[1] - hi_y, lo_y - tb[4]));
-        const double gz = fmax(0.0, fmax(tb[2] - hi_z, lo_z - tb[5]));
-        const double g2 = gx * gx + gy * gy + gz * gz;
+        const double gx = fmax(0.0, fmax(tb[0] - wh_x, wl_x - tb[3]));
+        const double gy = fmax(0.0, fmax(tb[1] - wh_y, wl_y - tb[4]));
+        const double gz = fmax(0.0, fmax(tb[2] - wh_z, wl_z - tb[5]));
+        const double g2 = gx * gx + gy * gy + gz * gz;  // wave-uniform
         if (g2 > rho2) {
             const float* Sp = sh[buf][3];
             float bw = 0.0f, bx = 0.0f, by = 0.0f, bz = 0.0f;
@@ -1678,7 +1687,6 @@ __global__ __launch_bounds__(kStepThreads) void step_update(StepArgs a) {
         }
     }
     const int lane = threadIdx.x & 63;
-    const double two_pi = 6.283185307179586476925286766559;
     uint32_t kept = 0;  // carrier mode: this wave's holes still travelling (wave-uniform)
     for (uint32_t base = blockIdx.x * kStepThreads; base < a.n_all;
          base += gridDim.x * kStepThreads) {
@@ -1709,7 +1717,21 @@ __global__ __launch_bounds__(kStepThreads) void step_update(StepArgs a) {
                     const float* pp = a.part + slot;
                     const size_t ps = a.pstride;
                     int c = 0;
-                    // four groups' loads in flight ahead of their adds (same order)
+                    // eight, then four groups' loads in flight ahead of their adds
+                    // (the adds in group order)
+                    for (; c + 8 <= nchunk; c += 8) {
+                        float v[8][3];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u)
+#pragma unroll
+                            for (int d = 0; d < 3; ++d) v[u][d] = pp[(size_t)((c + u) * 3 + d) * ps];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            sx += (double)v[u][0];
+                            sy += (double)v[u][1];
+                            sz += (double)v[u][2];
+                        }
+                    }
                     for (; c + 4 <= nchunk; c += 4) {
                         float v[4][3];
 #pragma unroll
@@ -1749,10 +1771,15 @@ __global__ __launch_bounds__(kStepThreads) void step_update(StepArgs a) {
                 const double x0 = a.x[j], y0 = a.y[j], z0 = a.z[j];
                 const double es = a.a1 * z0 - a.a2;
                 const double ex = ecx, ey = ecy, ez = ecz + es;
-                const double em = sqrt(ex * ex + ey * ey + ez * ez);
                 double mu = a.mu0;
-                if (a.mobility_model == 0)
-                    mu = a.mu0 / pow(1.0 + pow(em / a.ec, a.beta), a.inv_beta);
+                if (a.mobility_model == 0) {
+                    // Eq. (2), mu0 / (1 + (|E|/Ec)^beta)^(1/beta), as
+                    // mu0 exp(-log1p(y) / beta) with y = exp(beta (log|E|^2 / 2
+                    // - log Ec)): four transcendentals instead of two general
+                    // powers and a square root (|E| = 0 gives y = 0, mu = mu0)
+                    const double y = exp(a.beta * (0.5 * log(ex * ex + ey * ey + ez * ez) - a.log_ec));
+                    mu = a.mu0 * exp(-a.inv_beta * log1p(y));
+                }
                 // v = mu E in cm/s; v dt in cm; 1 cm = 1e4 um
                 double dx = mu * ex * a.dt_s * 1e4;
                 double dy = mu * ey * a.dt_s * 1e4;
@@ -1762,13 +1789,16 @@ __global__ __launch_bounds__(kStepThreads) void step_update(StepArgs a) {
                     philox4x32_10(w0, w1, w2, w3, a.key0, a.key1);
                     const double r01 = sqrt(-2.0 * log(unit_open(w0)));
                     const double r23 = sqrt(-2.0 * log(unit_open(w2)));
-                    const double ang1 = two_pi * unit_open(w1);
-                    const double ang3 = two_pi * unit_open(w3);
+                    // the angles 2 pi u in half-turns: 2 u is exact, and one
+                    // argument reduction serves both sine and cosine of the first
+                    double s1, c1;
+                    sincospi(2.0 * unit_open(w1), &s1, &c1);
+                    const double c3 = cospi(2.0 * unit_open(w3));
                     const double D = a.vt * mu;                        // Eq. (4), cm^2/s
                     const double sigma = sqrt(2.0 * D * a.dt_s) * 1e4;  // Eq. (3), um
-                    dx += sigma * (r01 * cos(ang1));
-                    dy += sigma * (r01 * sin(ang1));
-                    dz += sigma * (r23 * cos(ang3));
+                    dx += sigma * (r01 * c1);
+                    dy += sigma * (r01 * s1);
+                    dz += sigma * (r23 * c3);
                 }
                 const double xn = x0 + dx, yn = y0 + dy;
                 double zn = z0 + dz;

@@ -2,25 +2,25 @@
 // spatially (the keys are unique, so every correct sort gives the same
 // list).  A merge sort written for this list:
 //   block_sort  -- each workgroup sorts a tile of up to kSortTile keys
-//                  (bitonic network, in registers and LDS), giving sorted
-//                  runs of kSortTile (a list that fits one tile is sorted by
-//                  one workgroup sized to it);
+//                  (register sorts of kSortItems keys, then merge levels in
+//                  LDS), giving sorted runs of kSortTile (a list that fits
+//                  one tile is sorted by one workgroup sized to it);
 //   merge_runs  -- one launch per level doubles the run length: each
 //                  workgroup writes kSortTile consecutive outputs of one
 //                  merged pair of runs, locating its share of both runs by a
 //                  64-way search (one wave per end of its output range) and
 //                  merging it out of LDS, kSortItems outputs per thread.
 // A list of up to kSortTile keys takes one launch; 1e5 keys take one plus
-// six levels.  The kernels only read and write the two key buffers (no
+// five levels.  The kernels only read and write the two key buffers (no
 // memory-set commands, no temporary storage, no host synchronisation), so a
 // sequence of steps that sorts can be captured in a HIP graph.
 #include "gccd_internal.h"
 
 namespace gccd {
 
-constexpr int kSortThreads = 256;
+constexpr int kSortThreads = 512;
 constexpr int kSortItems = 8;
-constexpr uint32_t kSortTile = kSortThreads * kSortItems;  // 2048
+constexpr uint32_t kSortTile = kSortThreads * kSortItems;  // 4096
 
 __device__ __forceinline__ void compare_exchange(uint64_t& a, uint64_t& b, bool up) {
     if ((a > b) == up) {
@@ -30,61 +30,83 @@ __device__ __forceinline__ void compare_exchange(uint64_t& a, uint64_t& b, bool 
     }
 }
 
-// The bitonic network's compare-exchanges of partner distance j < kSortItems
-// for sequences of length k, on the thread's kSortItems consecutive keys
-// (global positions first, first + 1, ...): done in registers.
-__device__ __forceinline__ void register_stages(uint64_t (&v)[kSortItems], uint32_t first,
-                                                uint32_t k, uint32_t j_top) {
+// LDS slot of position i of a tile: one pad word after every kSortItems
+// keys, so that the kSortItems consecutive keys of each lane (a stride of
+// kSortItems + 1 words between lanes) spread over the banks.
+__device__ __forceinline__ uint32_t lds_slot(uint32_t i) { return i + i / kSortItems; }
+
+// Ascending sort of a lane's kSortItems keys in registers (bitonic network).
+__device__ __forceinline__ void register_sort(uint64_t (&v)[kSortItems]) {
 #pragma unroll
-    for (uint32_t j = kSortItems / 2; j > 0; j >>= 1) {
-        if (j > j_top) continue;
+    for (uint32_t k = 2; k <= (uint32_t)kSortItems; k <<= 1)
 #pragma unroll
-        for (uint32_t e = 0; e < (uint32_t)kSortItems; ++e)
-            if ((e & j) == 0u) compare_exchange(v[e], v[e | j], ((first + e) & k) == 0u);
-    }
+        for (uint32_t j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+            for (uint32_t e = 0; e < (uint32_t)kSortItems; ++e)
+                if ((e & j) == 0u) compare_exchange(v[e], v[e | j], (e & k) == 0u);
 }
 
-// One tile of T = THREADS * kSortItems keys sorted in LDS by a bitonic
-// network.  Partner distances below kSortItems stay inside a thread's
-// consecutive keys and run in registers; the others go through LDS, one
-// barrier each.
+// One tile of T = THREADS * kSortItems keys: each lane sorts kSortItems
+// consecutive keys in registers, then log2(T / kSortItems) levels merge
+// pairs of sorted runs in LDS, each lane writing kSortItems consecutive
+// outputs of its pair (found by a binary search on the merge path, then a
+// sequential merge).  Every level moves each key once through LDS (a bitonic
+// network moves it once per stage, log2 of the run length stages per
+// level).  Loads and stores of global memory are coalesced through LDS.
 template <int THREADS>
 __global__ __launch_bounds__(THREADS) void block_sort(const uint64_t* in, uint64_t* out,
                                                       uint32_t n) {
     constexpr uint32_t T = (uint32_t)THREADS * kSortItems;
-    __shared__ uint64_t s[T];
+    __shared__ uint64_t s[T + T / kSortItems];
     const uint32_t b0 = blockIdx.x * T;
     const uint32_t cnt = min(T, n - b0);
     const uint32_t first = threadIdx.x * kSortItems;
-    uint64_t v[kSortItems];
     // padding sorts last (a key equal to the padding value is the same value)
+    for (uint32_t i = threadIdx.x; i < T; i += THREADS)
+        s[lds_slot(i)] = i < cnt ? in[b0 + i] : ~0ull;
+    __syncthreads();
+    uint64_t v[kSortItems];
 #pragma unroll
-    for (uint32_t e = 0; e < (uint32_t)kSortItems; ++e)
-        v[e] = first + e < cnt ? in[b0 + first + e] : ~0ull;
+    for (uint32_t e = 0; e < (uint32_t)kSortItems; ++e) v[e] = s[lds_slot(first + e)];
+    register_sort(v);
+    for (uint32_t w = kSortItems; w < T; w <<= 1) {
+        __syncthreads();  // every read of s is done before it is written again
 #pragma unroll
-    for (uint32_t k = 2; k <= (uint32_t)kSortItems; k <<= 1) register_stages(v, first, k, k >> 1);
-    for (uint32_t k = 2 * kSortItems; k <= T; k <<= 1) {
-#pragma unroll
-        for (uint32_t e = 0; e < (uint32_t)kSortItems; ++e) s[first + e] = v[e];
+        for (uint32_t e = 0; e < (uint32_t)kSortItems; ++e) s[lds_slot(first + e)] = v[e];
         __syncthreads();
-        for (uint32_t j = k >> 1; j >= (uint32_t)kSortItems; j >>= 1) {
-            for (uint32_t p = threadIdx.x; p < T / 2; p += THREADS) {
-                const uint32_t i = 2 * p - (p & (j - 1));  // i has bit j clear
-                uint64_t a = s[i], b = s[i + j];
-                compare_exchange(a, b, (i & k) == 0u);
-                s[i] = a;
-                s[i + j] = b;
-            }
-            __syncthreads();
+        // outputs [k, k + kSortItems) of the merge of runs A = [base, base + w)
+        // and B = [base + w, base + 2 w) (both full: T is a power of two)
+        const uint32_t base = first / (2 * w) * (2 * w);
+        const uint32_t k = first - base, A = base, B = base + w;
+        uint32_t lo = k > w ? k - w : 0u, hi = min(k, w);
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (s[lds_slot(A + mid)] > s[lds_slot(B + k - 1u - mid)])
+                hi = mid;
+            else
+                lo = mid + 1u;
         }
+        uint32_t ia = lo, ib = k - lo;
+        uint64_t a = ia < w ? s[lds_slot(A + ia)] : ~0ull;
+        uint64_t b = ib < w ? s[lds_slot(B + ib)] : ~0ull;
 #pragma unroll
-        for (uint32_t e = 0; e < (uint32_t)kSortItems; ++e) v[e] = s[first + e];
-        register_stages(v, first, k, kSortItems / 2);
-        __syncthreads();  // every read of s is done before the next stage writes it
+        for (uint32_t e = 0; e < (uint32_t)kSortItems; ++e) {
+            if (ib >= w || (ia < w && a < b)) {
+                v[e] = a;
+                ++ia;
+                a = ia < w ? s[lds_slot(A + ia)] : ~0ull;
+            } else {
+                v[e] = b;
+                ++ib;
+                b = ib < w ? s[lds_slot(B + ib)] : ~0ull;
+            }
+        }
     }
+    __syncthreads();
 #pragma unroll
-    for (uint32_t e = 0; e < (uint32_t)kSortItems; ++e)
-        if (first + e < cnt) out[b0 + first + e] = v[e];
+    for (uint32_t e = 0; e < (uint32_t)kSortItems; ++e) s[lds_slot(first + e)] = v[e];
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < cnt; i += THREADS) out[b0 + i] = s[lds_slot(i)];
 }
 
 // Of the first k outputs of merging A[0, la) and B[0, lb) (sorted, no key in
@@ -128,7 +150,7 @@ __device__ uint32_t merge_split(const uint64_t* A, uint32_t la, const uint64_t* 
 // One merge level: runs of width w in `in` become runs of 2 w in `out`.
 __global__ __launch_bounds__(kSortThreads) void merge_runs(const uint64_t* in, uint64_t* out,
                                                           uint32_t n, uint32_t w) {
-    __shared__ uint64_t buf[kSortTile];
+    __shared__ uint64_t buf[kSortTile + kSortTile / kSortItems];
     __shared__ uint32_t cut[2];
     const uint64_t o0 = (uint64_t)blockIdx.x * kSortTile;  // first output of the workgroup
     const uint64_t base = o0 / (2ull * w) * (2ull * w);    // its pair of runs starts here
@@ -150,26 +172,40 @@ __global__ __launch_bounds__(kSortThreads) void merge_runs(const uint64_t* in, u
     for (uint32_t t = threadIdx.x; t < na + nb; t += kSortThreads)
         buf[t] = t < na ? A[i0 + t] : B[k0 - i0 + (t - na)];
     __syncthreads();
-    // outputs [kt, kt + kSortItems) of this workgroup's share
+    // outputs [kt, kt + kSortItems) of this workgroup's share, merged into
+    // registers, then stored through LDS so that the global stores coalesce
     const uint32_t kt = threadIdx.x * kSortItems;
-    if (kt >= na + nb) return;
-    const uint64_t* a = buf;
-    const uint64_t* b = buf + na;
-    uint32_t lo = kt > nb ? kt - nb : 0u, hi = min(kt, na);
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (a[mid] > b[kt - 1u - mid])
-            hi = mid;
-        else
-            lo = mid + 1u;
+    const uint32_t nk = na + nb;
+    uint64_t v[kSortItems];
+    if (kt < nk) {
+        const uint64_t* a = buf;
+        const uint64_t* b = buf + na;
+        uint32_t lo = kt > nb ? kt - nb : 0u, hi = min(kt, na);
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (a[mid] > b[kt - 1u - mid])
+                hi = mid;
+            else
+                lo = mid + 1u;
+        }
+        uint32_t ia = lo, ib = kt - lo;
+#pragma unroll
+        for (uint32_t e = 0; e < (uint32_t)kSortItems; ++e) {
+            if (kt + e < nk) {
+                const bool take_a = ib >= nb || (ia < na && a[ia] < b[ib]);
+                v[e] = take_a ? a[ia++] : b[ib++];
+            }
+        }
     }
-    uint32_t ia = lo, ib = kt - lo;
-    const uint32_t end = min(kt + kSortItems, na + nb);
+    __syncthreads();  // every read of buf is done
+    if (kt < nk) {
+#pragma unroll
+        for (uint32_t e = 0; e < (uint32_t)kSortItems; ++e)
+            if (kt + e < nk) buf[lds_slot(kt + e)] = v[e];
+    }
+    __syncthreads();
     uint64_t* o = out + base + k0;
-    for (uint32_t k = kt; k < end; ++k) {
-        const bool take_a = ib >= nb || (ia < na && a[ia] < b[ib]);
-        o[k] = take_a ? a[ia++] : b[ib++];
-    }
+    for (uint32_t t = threadIdx.x; t < nk; t += kSortThreads) o[t] = buf[lds_slot(t)];
 }
 
 // Sorts keys[0, n) (clobbered) into out[0, n).
@@ -186,6 +222,8 @@ hipError_t sort_keys(uint64_t* keys, uint64_t* out, uint32_t n, hipStream_t s) {
         block_sort<64><<<1, 64, 0, s>>>(keys, src, n);
     else if (n <= 128u * kSortItems)
         block_sort<128><<<1, 128, 0, s>>>(keys, src, n);
+    else if (n <= 256u * kSortItems)
+        block_sort<256><<<1, 256, 0, s>>>(keys, src, n);
     else
         block_sort<kSortThreads><<<tiles, kSortThreads, 0, s>>>(keys, src, n);
     hipError_t e = hipGetLastError();

@@ -104,7 +104,12 @@ def test_closure_parts_match_oracle(g, W, orc, n, seed):
     scale = np.max(np.abs(far_o))
     print(f"[closure] n={n} far: max |dF| / max |F| = {df.max() / scale:.2e}, "
           f"rms ratio {np.sqrt(np.mean(df**2)) / np.sqrt(np.mean(far_o**2)):.2e}", flush=True)
-    assert df.max() <= 2e-2 * scale
+    # Both sides round every activation to bf16 (a relative step of 2^-9) but
+    # accumulate in different orders, so a rounding can land on the other
+    # side of a step; allow three such steps at the largest output, and one
+    # in the rms.
+    assert df.max() <= 3 * 2.0**-9 * scale
+    assert np.sqrt(np.mean(df**2)) <= 2.0**-9 * np.sqrt(np.mean(far_o**2))
 
 
 def test_closure_field_is_its_parts(g, W):

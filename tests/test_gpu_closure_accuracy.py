@@ -1,12 +1,13 @@
 """The trained closure against the exact path on the same GPU.
 
 The acceptance bar is the one set for the closure: cloud second moments
-within 1 % of the exact path's.  The field error is reported relative to the
-rms of the exact far field, with a loose bound (5 %) that only catches a
-broken network or weight file; the closure's error floor from the
-discreteness of the far charges alone is 1.1 % at 3e4 holes and 0.7 % at
-1e5 (oracle, exact far field at the nodes).  Held-out seeds (2000 and up)
-only.
+within 1 % of the exact path's, checked on whole runs to collection at 1e5
+and at 1e6 holes (the closure's benchmark size).  The field error is
+reported relative to the rms of the exact far field and held to 1.5 %: the
+closure's error floor from the discreteness of the far charges alone is
+1.1 % at 3e4 holes and 0.7 % at 1e5 (oracle, exact far field at the nodes),
+and the trained network measures 1.08 % at 3e4 and 0.5-0.7 % above.
+Held-out seeds (2000 and up) only.
 """
 import os
 
@@ -76,14 +77,17 @@ def test_closure_field_error(g, W, weights, n, seed):
     err_tot = rms(Ec - Ee) / rms(Ee)
     print(f"[closure] n={n} seed={seed}: rms field error {err_far:.4f} of the rms far field "
           f"({err_tot:.4f} of the rms field)", flush=True)
-    assert err_far < 0.05
+    assert err_far < 0.015
 
 
-def test_closure_run_moments(g, W, weights):
-    """A 1e5-hole cloud 30 um deep run to collection both ways: variances of
-    the collected positions within 1 %, every hole collected, same charge."""
-    n, seed = 100000, 2004
-    x, y, z = W.gaussian_cloud(n, W.cloud_sigma(n), (480.0, 480.0, 30.0), seed, stream=2)
+@pytest.mark.parametrize("n,sigma,seed", [(100000, None, 2004), (1000000, 5.0, 2006)])
+def test_closure_run_moments(g, W, weights, n, sigma, seed):
+    """A cloud 30 um deep run to collection both ways (1e5 holes of the
+    single-cloud width; 1e6 holes of sigma 5 um, the closure's benchmark
+    cloud, made shallow to keep the exact run short): variances of the
+    collected positions within 1 %, every hole collected."""
+    sig = W.cloud_sigma(n) if sigma is None else sigma
+    x, y, z = W.gaussian_cloud(n, sig, (480.0, 480.0, 30.0), seed, stream=2)
     d = dict(W.DEVICE, event=seed)
     out = {}
     for name, wt in (("exact", None), ("closure", weights)):

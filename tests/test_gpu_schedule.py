@@ -188,3 +188,22 @@ def test_full_size_schedules_agree(g, W):
     print(f"[schedule] cloud n=100000: graph replays {st['graph_replays']}, usable "
           f"{st['graph_usable']}", flush=True)
     assert st["graph_usable"] == 1 and st["graph_replays"] == 2
+
+
+def test_full_batch_schedules_agree(g, W):
+    """The 4096-cloud batch (1.8e7 holes) under the three schedules, two
+    32-step stretches: the graph is captured at this size (the per-step sort
+    issues no memory-set command) and replayed, and every stretch is bit
+    for bit the grid schedule's."""
+    events = W.batch_of_clouds(4096, seed=1)
+    off = np.concatenate([[0], np.cumsum([len(e[0]) for e in events])]).astype(np.int64)
+    x = np.concatenate([e[0] for e in events])
+    y = np.concatenate([e[1] for e in events])
+    z = np.concatenate([e[2] for e in events])
+    d = dict(W.DEVICE)
+    runs = {s: stretches(g, d, x, y, z, s, offsets=list(off), n_stretch=2) for s in SCHEDULES}
+    compare(runs, "batch 4096")
+    st = runs["graph"][1]
+    print(f"[schedule] batch of 4096 ({len(x)} holes): graph replays {st['graph_replays']}, "
+          f"usable {st['graph_usable']}", flush=True)
+    assert st["graph_usable"] == 1 and st["graph_replays"] == 2
