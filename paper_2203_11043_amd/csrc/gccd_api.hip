@@ -29,15 +29,13 @@ constexpr int kPoll = 32;                       // steps between host reads of t
 constexpr int64_t kMaxCarriers = 2147483647LL;  // slots are 32-bit
 
 // Device block of counters (32-bit words): a ring of three travelling-hole
-// counts by step mod 3 (carrier mode), the non-finite flag, the step after
-// the last step with travelling holes, two uint64 statistics and the two
-// uint64 counts of the coming step (list mode).
+// counts by step mod 3, the non-finite flag, the step after the last step
+// with travelling holes and two uint64 statistics.
 enum : int {
     kMetaCount = 0,
     kMetaFlag = 3,
     kMetaLast = 4,
     kMetaStats = 8,
-    kMetaPending = 12,
     kMetaWords = 16
 };
 // words of the schedule buffer (device, and a pinned host copy to upload from)
@@ -81,8 +79,22 @@ struct gccd_ctx {
     double* z = nullptr;
     int32_t* cstep = nullptr;
     uint32_t* ev_of = nullptr;
+    // The sorted lists.  keys[cur] is the list the next step runs over;
+    // the step kernel writes every slot's new key into ukeys[u], which is
+    // sorted into a list.  Steps of the exact path with every hole a source
+    // are pipelined: the sort of the keys of step s+1's positions runs on the
+    // side stream while step s+1 runs over the list of step s (the list only
+    // orders the work; the travelling holes are told by their collection
+    // step), and is used from step s+2 on.  Other steps sort before the next
+    // step (the list then holds the positions it runs over).
     uint64_t* keys[2] = {nullptr, nullptr};
+    uint64_t* ukeys[2] = {nullptr, nullptr};
     int cur = 0;
+    int u = 0;
+    bool sorting = false;            // the side stream sorts into keys[cur ^ 1]
+    hipStream_t side = nullptr;      // default priority, like every stream here
+    hipEvent_t ev_keys = nullptr;    // the step kernel has written ukeys
+    hipEvent_t ev_list = nullptr;    // the side stream's list and counts are done
     double* ps[3] = {nullptr, nullptr, nullptr};
     double* tile_box = nullptr;
     float* part = nullptr;
@@ -90,7 +102,7 @@ struct gccd_ctx {
     uint32_t* ev_off_d = nullptr;
     uint32_t* ev_tile_d = nullptr;
     uint32_t* tile_event_d = nullptr;
-    uint32_t* ev_active_d = nullptr;
+    uint32_t* ev_active_d[2] = {nullptr, nullptr};  // travelling holes per event, by list
     int32_t* ev_chunks_d = nullptr;
     FieldItem* items_d = nullptr;
     size_t items_cap = 0;
@@ -135,6 +147,7 @@ struct gccd_ctx {
     hipStream_t cap_stream = nullptr; // captures are recorded here (the context's stream
                                       // may be the null stream, which cannot capture)
     bool graph_refused = false;      // a capture for this load failed or held a memset node
+    int graph_cur = -1, graph_u = -1;  // the list buffers the captured steps start from
     int64_t graph_replays = 0;
 
     bool timing = false;
@@ -206,8 +219,10 @@ void drop_graph(gccd_ctx* c) {
 }
 
 void free_buffers(gccd_ctx* c) {
+    if (c->side) (void)hipStreamSynchronize(c->side);  // a list may still be sorting
     drop_graph(c);
     c->graph_refused = false;
+    c->sorting = false;
     dfree(c->x);
     dfree(c->y);
     dfree(c->z);
@@ -215,6 +230,8 @@ void free_buffers(gccd_ctx* c) {
     dfree(c->ev_of);
     dfree(c->keys[0]);
     dfree(c->keys[1]);
+    dfree(c->ukeys[0]);
+    dfree(c->ukeys[1]);
     for (auto& q : c->ps) dfree(q);
     dfree(c->tile_box);
     dfree(c->part);
@@ -222,7 +239,8 @@ void free_buffers(gccd_ctx* c) {
     dfree(c->ev_off_d);
     dfree(c->ev_tile_d);
     dfree(c->tile_event_d);
-    dfree(c->ev_active_d);
+    dfree(c->ev_active_d[0]);
+    dfree(c->ev_active_d[1]);
     dfree(c->ev_chunks_d);
     dfree(c->items_d);
     hfree(c->host_active);
@@ -515,7 +533,7 @@ FieldArgs field_args(const gccd_ctx* c, bool targets_all) {
     FieldArgs fa{};
     fa.items = c->items_d;
     fa.ev_off = c->ev_off_d;
-    fa.ev_active = c->ev_active_d;
+    fa.ev_active = c->ev_active_d[c->cur];
     fa.ev_tile = c->ev_tile_d;
     fa.targets_all = targets_all ? 1 : 0;
     fa.sources_all = c->p.collected_are_sources;
@@ -551,28 +569,41 @@ uint32_t queue_grid(gccd_ctx* c) {
     return (uint32_t)std::max<size_t>(1, std::min(slots, c->items_cap));
 }
 
-// The sorted list from keys already written to keys[cur ^ 1]: sort into
-// keys[cur], count each event's travelling holes, gather the positions.
-int finish_list(gccd_ctx* c) {
-    const uint32_t n = (uint32_t)c->n;
-    GCCD_HIP(c, sort_keys(c->keys[c->cur ^ 1], c->keys[c->cur], n, c->stream));
-    GCCD_HIP(c, launch_count(c->keys[c->cur], c->ev_off_d, c->n_events, c->kl,
-                             c->p.collected_are_sources,
-                             c->ev_active_d,
-                             reinterpret_cast<unsigned long long*>(c->meta + kMetaPending),
-                             c->stream));
+// The current positions in the slot order of keys[cur], and the boxes of
+// its source tiles.
+int gather(gccd_ctx* c) {
     GCCD_HIP(c, launch_gather(c->keys[c->cur], c->ev_off_d, c->ev_tile_d, c->tile_event_d,
-                              c->ev_active_d, c->p.collected_are_sources, c->n_tiles, c->kl, c->x,
-                              c->y, c->z, c->ps[0], c->ps[1], c->ps[2], c->tile_box,
+                              c->ev_active_d[c->cur], c->p.collected_are_sources, c->n_tiles,
+                              c->kl, c->x, c->y, c->z, c->ps[0], c->ps[1], c->ps[2], c->tile_box,
                               std::max<uint32_t>(c->n_tiles, 1), c->stream));
     return GCCD_OK;
+}
+
+// The sorted list from the keys in `unsorted` (clobbered): sort into
+// keys[cur], count each event's travelling holes, gather the positions.
+int finish_list(gccd_ctx* c, uint64_t* unsorted) {
+    const uint32_t n = (uint32_t)c->n;
+    GCCD_HIP(c, sort_keys(unsorted, c->keys[c->cur], n, c->stream));
+    GCCD_HIP(c, launch_count(c->keys[c->cur], c->ev_off_d, c->n_events, c->kl,
+                             c->ev_active_d[c->cur], c->stream));
+    return gather(c);
+}
+
+// Leaves the pipelined state: the list being sorted on the side stream (the
+// one of the current positions) becomes the current list.
+int settle(gccd_ctx* c) {
+    if (!c->sorting) return GCCD_OK;
+    GCCD_HIP(c, hipStreamWaitEvent(c->stream, c->ev_list, 0));
+    c->cur ^= 1;
+    c->sorting = false;
+    return gather(c);
 }
 
 int read_counts(gccd_ctx* c) {
     GCCD_HIP(c, hipMemcpyAsync(c->host_meta, c->meta, kMetaWords * sizeof(uint32_t),
                                hipMemcpyDeviceToHost, c->stream));
     if (c->list_mode)
-        GCCD_HIP(c, hipMemcpyAsync(c->host_active, c->ev_active_d,
+        GCCD_HIP(c, hipMemcpyAsync(c->host_active, c->ev_active_d[c->cur],
                                    c->n_events * sizeof(uint32_t), hipMemcpyDeviceToHost,
                                    c->stream));
     GCCD_HIP(c, hipStreamSynchronize(c->stream));
@@ -788,6 +819,10 @@ namespace {
 template <typename Issue>
 int capture_steps(gccd_ctx* c, Issue& issue) {
     drop_graph(c);
+    // issuing advances the list state; nothing runs while capturing, so it is
+    // put back (a full stretch leaves it as it was; a refused one need not)
+    const int cur0 = c->cur, u0 = c->u;
+    const bool sorting0 = c->sorting;
     if (!c->cap_stream) GCCD_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     c->ev_used = 0;
     hipStream_t user = c->stream;
@@ -801,6 +836,9 @@ int capture_steps(gccd_ctx* c, Issue& issue) {
     }
     c->stream = user;
     c->ev_used = 0;
+    c->cur = cur0;
+    c->u = u0;
+    c->sorting = sorting0;
     bool ok = r == GCCD_OK && e == hipSuccess && g != nullptr;
     if (ok) {
         size_t nn = 0;
@@ -910,6 +948,9 @@ void gccd_destroy(gccd_ctx* c) {
     (void)hipFree(c->sched);
     (void)hipHostFree(c->host_sched);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->side) (void)hipStreamDestroy(c->side);
+    if (c->ev_keys) (void)hipEventDestroy(c->ev_keys);
+    if (c->ev_list) (void)hipEventDestroy(c->ev_list);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     delete c;
 }
@@ -965,6 +1006,8 @@ int gccd_load_events(gccd_ctx* c, int32_t n_events, const int64_t* offsets, cons
               hipMalloc(&c->ev_of, (size_t)n * sizeof(uint32_t)) == hipSuccess &&
               hipMalloc(&c->keys[0], (size_t)n * sizeof(uint64_t)) == hipSuccess &&
               hipMalloc(&c->keys[1], (size_t)n * sizeof(uint64_t)) == hipSuccess &&
+              hipMalloc(&c->ukeys[0], (size_t)n * sizeof(uint64_t)) == hipSuccess &&
+              hipMalloc(&c->ukeys[1], (size_t)n * sizeof(uint64_t)) == hipSuccess &&
               hipMalloc(&c->ps[0], d) == hipSuccess && hipMalloc(&c->ps[1], d) == hipSuccess &&
               hipMalloc(&c->ps[2], d) == hipSuccess &&
               hipMalloc(&c->tile_box, kBoxRows * sizeof(double) * tile_event.size()) ==
@@ -972,7 +1015,8 @@ int gccd_load_events(gccd_ctx* c, int32_t n_events, const int64_t* offsets, cons
               hipMalloc(&c->ev_off_d, (E + 1) * sizeof(uint32_t)) == hipSuccess &&
               hipMalloc(&c->ev_tile_d, (E + 1) * sizeof(uint32_t)) == hipSuccess &&
               hipMalloc(&c->tile_event_d, tile_event.size() * sizeof(uint32_t)) == hipSuccess &&
-              hipMalloc(&c->ev_active_d, E * sizeof(uint32_t)) == hipSuccess &&
+              hipMalloc(&c->ev_active_d[0], E * sizeof(uint32_t)) == hipSuccess &&
+              hipMalloc(&c->ev_active_d[1], E * sizeof(uint32_t)) == hipSuccess &&
               hipMalloc(&c->ev_chunks_d, E * sizeof(int32_t)) == hipSuccess &&
               hipHostMalloc((void**)&c->host_active, E * sizeof(uint32_t)) == hipSuccess;
     if (!ok) {
@@ -1003,17 +1047,18 @@ int gccd_load_events(gccd_ctx* c, int32_t n_events, const int64_t* offsets, cons
                             c->p.thickness_um, c->p.well_z_um, c->meta + kMetaCount, c->stream));
     c->list_mode = c->p.coulomb != 0;
     c->cur = 0;
+    c->u = 0;
     if (c->list_mode) {
         GCCD_HIP(c, launch_make_keys(c->x, c->y, c->z, c->cstep, c->ev_of, c->ev_off_d,
-                                     (uint32_t)n, c->kl, c->keys[1], c->stream));
-        int r = finish_list(c);
+                                     (uint32_t)n, c->kl, c->ukeys[0], c->stream));
+        int r = finish_list(c, c->ukeys[0]);
         if (r != GCCD_OK) return r;
     }
     {
         int r = read_counts(c);
         if (r != GCCD_OK) return r;
     }
-    c->n_active = c->list_mode ? (int64_t)meta64(c, kMetaPending) : c->host_meta[kMetaCount];
+    c->n_active = c->host_meta[kMetaCount];
     c->step = 0;
     c->loaded = true;
     c->field_ms = 0;
@@ -1143,10 +1188,12 @@ int gccd_closure_parts(gccd_ctx* c, double* near_x, double* near_y, double* near
     if (r != GCCD_OK) return r;
     if (!c->list_mode) {
         GCCD_HIP(c, launch_make_keys(c->x, c->y, c->z, c->cstep, c->ev_of, c->ev_off_d, n, c->kl,
-                                     c->keys[c->cur ^ 1], c->stream));
-        r = finish_list(c);
-        if (r != GCCD_OK) return r;
+                                     c->ukeys[0], c->stream));
+        r = finish_list(c, c->ukeys[0]);
+    } else {
+        r = gather(c);  // the current positions in the order of the current list
     }
+    if (r != GCCD_OK) return r;
     choose_near_chunks(c);
     r = ensure_closure_capacity(c);
     if (r == GCCD_OK) r = build_near_items(c, n);
@@ -1281,7 +1328,7 @@ int gccd_run(gccd_ctx* c, double dt_ps, int64_t max_steps, int64_t* steps_done,
     sa.cstep = c->cstep;
     sa.list_mode = c->list_mode ? 1 : 0;
     sa.ev_off = c->ev_off_d;
-    sa.ev_active = c->ev_active_d;
+    sa.sources_all = c->p.collected_are_sources;
     sa.ev_chunks = c->ev_chunks_d;
     sa.ev_of = c->ev_of;
     sa.kl = c->kl;
@@ -1307,9 +1354,37 @@ int gccd_run(gccd_ctx* c, double dt_ps, int64_t max_steps, int64_t* steps_done,
     sa.key1 = (uint32_t)(c->p.seed >> 32);
     sa.close = c->list_mode ? c->close : nullptr;
     sa.close_unit = std::ldexp(1.0 / (c->p.softening_um * c->p.softening_um), -kExactShift);
-    sa.pending = reinterpret_cast<const unsigned long long*>(c->meta + kMetaPending);
+    sa.cnt_ring = c->meta + kMetaCount;
     sa.stats = reinterpret_cast<unsigned long long*>(c->meta + kMetaStats);
     sa.misc = reinterpret_cast<int32_t*>(c->meta + kMetaFlag);
+
+    // Exact steps with every hole a source are pipelined (see gccd_ctx::keys);
+    // the others need the list of the positions they run over.
+    const bool pipelined = c->list_mode && !use_closure && c->p.collected_are_sources;
+    if (c->list_mode && !pipelined) {
+        int r = settle(c);
+        if (r != GCCD_OK) return r;
+    }
+    if (pipelined && !c->side) {
+        GCCD_HIP(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+        GCCD_HIP(c, hipEventCreateWithFlags(&c->ev_keys, hipEventDisableTiming));
+        GCCD_HIP(c, hipEventCreateWithFlags(&c->ev_list, hipEventDisableTiming));
+    }
+    if (pipelined && !c->sorting && bound > 0) {
+        // Enter the steady state: the next step's list (the current one) also
+        // stands in keys[cur ^ 1] as if the side stream had sorted it.  The
+        // next two steps run over the same list either way, so results do not
+        // change; every stretch then starts alike and can be captured.
+        const size_t kb = (size_t)c->n * sizeof(uint64_t);
+        GCCD_HIP(c, hipMemcpyAsync(c->keys[c->cur ^ 1], c->keys[c->cur], kb,
+                                   hipMemcpyDeviceToDevice, c->stream));
+        GCCD_HIP(c, hipMemcpyAsync(c->ev_active_d[c->cur ^ 1], c->ev_active_d[c->cur],
+                                   c->n_events * sizeof(uint32_t), hipMemcpyDeviceToDevice,
+                                   c->stream));
+        GCCD_HIP(c, hipEventRecord(c->ev_list, c->stream));
+        c->sorting = true;
+    }
+    int64_t stretch = 0;  // steps of the stretch being issued
 
     // One time step: in list mode step i of the current stretch (its index is
     // the base in sched[kSchedStep] plus i), else absolute step s.
@@ -1317,6 +1392,10 @@ int gccd_run(gccd_ctx* c, double dt_ps, int64_t max_steps, int64_t* steps_done,
     auto issue = [&](uint32_t i, uint32_t s) -> int {
         if (c->list_mode) {
             sa.step = i;
+            if (pipelined) {
+                int r = gather(c);  // this step's positions in the order of keys[cur]
+                if (r != GCCD_OK) return r;
+            }
             hipEvent_t* evp = nullptr;
             int r = record_field_start(c, &evp);
             if (r != GCCD_OK) return r;
@@ -1330,14 +1409,31 @@ int gccd_run(gccd_ctx* c, double dt_ps, int64_t max_steps, int64_t* steps_done,
             }
             if (evp) GCCD_HIP(c, hipEventRecord(evp[1], c->stream));
             sa.keys_in = c->keys[c->cur];
-            sa.keys_out = c->keys[c->cur ^ 1];
+            sa.keys_out = c->ukeys[c->u];
+            sa.ev_active = c->ev_active_d[c->cur];
             GCCD_HIP(c, launch_step(sa, n, c->stream));
-            return finish_list(c);  // next step's sorted list, counts, positions
+            if (!pipelined) return finish_list(c, c->ukeys[c->u]);  // the next step's list
+            // The list of the new positions is sorted on the side stream while
+            // the next step runs over the one the side stream finished last
+            // (the first step of a stretch follows the join of the last one).
+            GCCD_HIP(c, hipEventRecord(c->ev_keys, c->stream));
+            if (c->sorting) {
+                if (i != 0) GCCD_HIP(c, hipStreamWaitEvent(c->stream, c->ev_list, 0));
+                c->cur ^= 1;
+            }
+            const int dst = c->cur ^ 1;  // the list the step just finished used, or a free one
+            GCCD_HIP(c, hipStreamWaitEvent(c->side, c->ev_keys, 0));
+            GCCD_HIP(c, sort_keys(c->ukeys[c->u], c->keys[dst], n, c->side));
+            GCCD_HIP(c, launch_count(c->keys[dst], c->ev_off_d, c->n_events, c->kl,
+                                     c->ev_active_d[dst], c->side));
+            GCCD_HIP(c, hipEventRecord(c->ev_list, c->side));
+            c->sorting = true;
+            c->u ^= 1;
+            if ((int64_t)i + 1 == stretch)  // join: the stretch ends with its last sort done
+                GCCD_HIP(c, hipStreamWaitEvent(c->stream, c->ev_list, 0));
+            return GCCD_OK;
         }
         sa.step = s;
-        sa.cnt_in = c->meta + kMetaCount + (s % 3u);
-        sa.cnt_out = c->meta + kMetaCount + ((s + 1u) % 3u);
-        sa.cnt_clear = c->meta + kMetaCount + ((s + 2u) % 3u);
         GCCD_HIP(c, launch_step(sa, n, c->stream));
         return GCCD_OK;
     };
@@ -1355,11 +1451,17 @@ int gccd_run(gccd_ctx* c, double dt_ps, int64_t max_steps, int64_t* steps_done,
             GCCD_HIP(c, hipMemcpyAsync(c->sched + kSchedStep, c->host_sched + kSchedStep,
                                        sizeof(uint32_t), hipMemcpyHostToDevice, c->stream));
         }
+        stretch = chunk_steps;
         bool replayed = false;
+        // a pipelined stretch is replayed from the list buffers it was
+        // captured from (an even stretch leaves them as it found them)
         if (graphable && chunk_steps == kPoll && !c->graph_refused) {
+            if (c->graph_exec && (c->graph_cur != c->cur || c->graph_u != c->u)) drop_graph(c);
             if (!c->graph_exec) {
                 int r = capture_steps(c, issue);
                 if (r != GCCD_OK) return r;
+                c->graph_cur = c->cur;
+                c->graph_u = c->u;
             }
             if (c->graph_exec) {
                 GCCD_HIP(c, hipGraphLaunch(c->graph_exec, c->stream));
@@ -1380,10 +1482,7 @@ int gccd_run(gccd_ctx* c, double dt_ps, int64_t max_steps, int64_t* steps_done,
             r = collect_timing(c);
             if (r != GCCD_OK) return r;
         }
-        if (c->list_mode)
-            bound = (int64_t)meta64(c, kMetaPending);
-        else
-            bound = c->host_meta[kMetaCount + (uint32_t)(step0 + k) % 3u];
+        bound = c->host_meta[kMetaCount + (uint32_t)(step0 + k) % 3u];
         if (c->host_meta[kMetaFlag] != 0) {
             c->step = (int64_t)(uint32_t)c->host_meta[kMetaLast];
             c->n_active = bound;
@@ -1413,11 +1512,16 @@ int gccd_field(gccd_ctx* c, double* ex, double* ey, double* ez) {
     if (!ex || !ey || !ez) return fail(c, GCCD_E_INVALID, "gccd_field: NULL pointer");
     const uint32_t n = (uint32_t)c->n;
     GCCD_HIP(c, hipStreamSynchronize(c->stream));  // the item staging buffer is free
-    if (!c->list_mode) {
-        // no list is kept without Coulomb repulsion: build one for this call
-        GCCD_HIP(c, launch_make_keys(c->x, c->y, c->z, c->cstep, c->ev_of, c->ev_off_d, n, c->kl,
-                                     c->keys[c->cur ^ 1], c->stream));
-        int r = finish_list(c);
+    {
+        int r;
+        if (!c->list_mode) {
+            // no list is kept without Coulomb repulsion: build one for this call
+            GCCD_HIP(c, launch_make_keys(c->x, c->y, c->z, c->cstep, c->ev_of, c->ev_off_d, n,
+                                         c->kl, c->ukeys[0], c->stream));
+            r = finish_list(c, c->ukeys[0]);
+        } else {
+            r = gather(c);  // the current positions in the order of the current list
+        }
         if (r != GCCD_OK) return r;
     }
     if (closure_applies(c)) {
@@ -1653,8 +1757,7 @@ int gccd_field_noalloc(const gccd_params* p, int64_t n, const double* x, const d
                        meta + kMetaCount, st));
     NA_HIP(launch_make_keys(cx, cy, cz, cstep, ev_of, ev_off, nn, kl, keys1, st));
     NA_HIP(sort_keys(keys1, keys0, nn, st));
-    NA_HIP(launch_count(keys0, ev_off, 1u, kl, p->collected_are_sources, ev_active,
-                        reinterpret_cast<unsigned long long*>(meta + kMetaPending), st));
+    NA_HIP(launch_count(keys0, ev_off, 1u, kl, ev_active, st));
     NA_HIP(launch_gather(keys0, ev_off, ev_tile, tile_event, ev_active, p->collected_are_sources,
                          (uint32_t)tiles, kl, cx, cy, cz, px, py, pz, box, (uint32_t)tiles, st));
     FieldArgs fa{};

@@ -93,10 +93,13 @@ struct StepArgs {
     double* z;
     int32_t* cstep;
     int32_t list_mode;         // 1: slots of the sorted list (Coulomb on); 0: carriers
-    const uint64_t* keys_in;   // this step's sorted list (list mode)
-    uint64_t* keys_out;        // next step's list, before sorting (list mode)
+    const uint64_t* keys_in;   // the list this step runs over (list mode; its segments
+                               // may be one step old: a hole travels while cstep < 0)
+    uint64_t* keys_out;        // every slot's new key, before sorting (list mode)
     const uint32_t* ev_off;    // [E+1]
-    const uint32_t* ev_active; // [E] (list mode)
+    const uint32_t* ev_active; // [E] travelling holes of each event in keys_in (list mode)
+    int32_t sources_all;       // sources of a target's Eq. (6) sum: its whole event, or
+                               // (0) the ev_active travelling holes
     const int32_t* ev_chunks;  // [E] chunks of each event's field sum (list mode)
     const uint32_t* ev_of;     // [n] event of each carrier (carrier mode)
     KeyLayout kl;
@@ -117,13 +120,10 @@ struct StepArgs {
                                // the same arguments at a new base)
     uint32_t event0;          // Philox event word of event 0
     uint32_t key0, key1;
-    const uint32_t* cnt_in;   // carrier mode: travelling holes at the start of the step
-    uint32_t* cnt_out;        // carrier mode: ... of the next step (zeroed beforehand)
-    uint32_t* cnt_clear;      // carrier mode: counter of the step after next
+    uint32_t* cnt_ring;       // [3] travelling holes at the start of step s in [s % 3]
     unsigned long long* close;  // list mode: the exactly summed close terms by slot
                                 // ([3][pstride]); read and cleared
     double close_unit;          // um^-2 per fixed-point unit of close
-    const unsigned long long* pending;  // list mode: [0] holes, [1] pairs of this step
     unsigned long long* stats;  // [0] carrier-steps, [1] pair interactions
     int32_t* misc;              // [0] non-finite flag, [1] step after the last busy one
 };
@@ -149,8 +149,7 @@ hipError_t launch_gather(const uint64_t* keys, const uint32_t* ev_off, const uin
                          const double* z, double* px, double* py, double* pz, double* box,
                          uint32_t stride, hipStream_t s);
 hipError_t launch_count(const uint64_t* keys, const uint32_t* ev_off, uint32_t n_events,
-                        KeyLayout kl, int sources_all, uint32_t* ev_active,
-                        unsigned long long* pending, hipStream_t s);
+                        KeyLayout kl, uint32_t* ev_active, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
 // Sums the partial groups [g0, g0 + ev_chunks[e]) (or [g0, g0 + groups) when
 // groups > 0) of every slot and writes K times the sum in carrier order.

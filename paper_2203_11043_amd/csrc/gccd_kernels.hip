@@ -1469,16 +1469,14 @@ hipError_t launch_make_keys(const double* x, const double* y, const double* z,
     return hipGetLastError();
 }
 
-// SINGLE: one workgroup of kCountThreads covers every event and writes the
-// totals itself (no clearing launch before it); otherwise the totals are
-// cleared beforehand and every thread adds its events' counts atomically.
+// The travelling holes of each event: the first collected key of its
+// segment (travelling holes come first), by binary search.
 constexpr int kCountThreads = 256;
 
-template <bool SINGLE>
-__global__ __launch_bounds__(kCountThreads) void count_active(
-    const uint64_t* keys, const uint32_t* ev_off, uint32_t n_events, KeyLayout kl,
-    int sources_all, uint32_t* ev_active, unsigned long long* pending) {
-    unsigned long long holes = 0, pairs = 0;
+__global__ __launch_bounds__(kCountThreads) void count_active(const uint64_t* keys,
+                                                              const uint32_t* ev_off,
+                                                              uint32_t n_events, KeyLayout kl,
+                                                              uint32_t* ev_active) {
     for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n_events;
          e += gridDim.x * blockDim.x) {
         const uint32_t off = ev_off[e], ne = ev_off[e + 1] - off;
@@ -1491,46 +1489,13 @@ __global__ __launch_bounds__(kCountThreads) void count_active(
                 lo = mid + 1;
         }
         ev_active[e] = lo;
-        const unsigned long long src = sources_all ? ne : lo;
-        if (SINGLE) {
-            holes += lo;
-            pairs += (unsigned long long)lo * src;
-        } else if (lo > 0) {
-            atomicAdd(&pending[0], (unsigned long long)lo);
-            atomicAdd(&pending[1], (unsigned long long)lo * src);
-        }
-    }
-    if (SINGLE) {
-        __shared__ unsigned long long red[2][kCountThreads];
-        red[0][threadIdx.x] = holes;
-        red[1][threadIdx.x] = pairs;
-        __syncthreads();
-        for (int h = kCountThreads / 2; h > 0; h >>= 1) {
-            if ((int)threadIdx.x < h) {
-                red[0][threadIdx.x] += red[0][threadIdx.x + h];
-                red[1][threadIdx.x] += red[1][threadIdx.x + h];
-            }
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            pending[0] = red[0][0];
-            pending[1] = red[1][0];
-        }
     }
 }
 
 hipError_t launch_count(const uint64_t* keys, const uint32_t* ev_off, uint32_t n_events,
-                        KeyLayout kl, int sources_all, uint32_t* ev_active,
-                        unsigned long long* pending, hipStream_t s) {
-    if (n_events <= (uint32_t)kCountThreads) {
-        count_active<true><<<1, kCountThreads, 0, s>>>(keys, ev_off, n_events, kl, sources_all,
-                                                        ev_active, pending);
-        return hipGetLastError();
-    }
-    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(pending), 4, 0u, s);
-    if (e != hipSuccess) return e;
-    count_active<false><<<grid_for(n_events, kCountThreads, 1024), kCountThreads, 0, s>>>(
-        keys, ev_off, n_events, kl, sources_all, ev_active, pending);
+                        KeyLayout kl, uint32_t* ev_active, hipStream_t s) {
+    count_active<<<grid_for(n_events, kCountThreads, 1024), kCountThreads, 0, s>>>(
+        keys, ev_off, n_events, kl, ev_active);
     return hipGetLastError();
 }
 
@@ -1671,38 +1636,49 @@ __device__ __forceinline__ double unit_open(uint32_t w) {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kStepThreads) void step_update(StepArgs a) {
     const uint32_t step = a.step + (a.step_base ? *a.step_base : 0u);
+    // travelling holes at the start of this step, of the next one, and the
+    // counter of the step after next (cleared now; nobody reads it)
+    const uint32_t* cnt_in = a.cnt_ring + step % 3u;
+    uint32_t* cnt_out = a.cnt_ring + (step + 1u) % 3u;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        unsigned long long holes, pairs = 0;
-        if (a.list_mode) {
-            holes = a.pending[0];
-            pairs = a.pending[1];
-        } else {
-            holes = *a.cnt_in;
-            *a.cnt_clear = 0u;  // counter of the step after next; nobody reads it now
-        }
+        const unsigned long long holes = *cnt_in;
+        a.cnt_ring[(step + 2u) % 3u] = 0u;
         if (holes > 0) {
             atomicAdd(&a.stats[0], holes);
-            if (a.coulomb) atomicAdd(&a.stats[1], pairs);
             a.misc[1] = (int32_t)(step + 1u);
         }
     }
     const int lane = threadIdx.x & 63;
-    uint32_t kept = 0;  // carrier mode: this wave's holes still travelling (wave-uniform)
+    uint32_t kept = 0;  // this wave's holes still travelling (wave-uniform)
+    unsigned long long pairs = 0;  // this lane's pair interactions of Eq. (6)
     for (uint32_t base = blockIdx.x * kStepThreads; base < a.n_all;
          base += gridDim.x * kStepThreads) {
         const uint32_t slot = base + threadIdx.x;
         bool keep = false;
         if (slot < a.n_all) {
-            uint32_t e, j, local;
+            uint32_t e, j, local, src = 0u;
             bool active;
             uint64_t key = 0;
             if (a.list_mode) {
+                // the list may be one step old (its travelling segment then
+                // still holds the holes collected in the last step): the
+                // carrier's own collection step decides
                 key = a.keys_in[slot];
                 e = key_event(key, a.kl);
                 const uint32_t off = a.ev_off[e], ne = a.ev_off[e + 1] - off;
                 local = min(key_local(key, a.kl), ne - 1u);
                 j = off + local;
-                active = slot - off < a.ev_active[e];
+                active = a.cstep[j] < 0;
+                if (active) {
+                    src = a.sources_all ? ne : a.ev_active[e];
+                } else if (a.close && slot - off < a.ev_active[e]) {
+                    // a target of the field launch collected in the last step:
+                    // its close-pair sums are not consumed, so cleared here
+                    const size_t ps = a.pstride;
+                    a.close[slot] = 0ull;
+                    a.close[slot + ps] = 0ull;
+                    a.close[slot + 2 * ps] = 0ull;
+                }
             } else {
                 j = slot;
                 e = a.ev_of[j];
@@ -1710,6 +1686,7 @@ __global__ __launch_bounds__(kStepThreads) void step_update(StepArgs a) {
                 active = a.cstep[j] < 0;
             }
             if (active) {
+                pairs += src;  // sources of the Eq. (6) sum at this target
                 double ecx = 0.0, ecy = 0.0, ecz = 0.0;
                 if (a.coulomb) {
                     double sx = 0.0, sy = 0.0, sz = 0.0;
@@ -1814,19 +1791,28 @@ __global__ __launch_bounds__(kStepThreads) void step_update(StepArgs a) {
             }
             if (a.list_mode) a.keys_out[slot] = key;
         }
-        if (!a.list_mode) kept += (uint32_t)__popcll(__ballot(keep));
+        kept += (uint32_t)__popcll(__ballot(keep));
     }
-    if (!a.list_mode) {
-        // one atomic per workgroup: a counter taking one per wave and grid-
-        // stride turn (2.6e5 at 2^24 holes) serialised the whole step
-        __shared__ uint32_t wave_kept[kStepThreads / 64];
-        if (lane == 0) wave_kept[threadIdx.x >> 6] = kept;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t t = 0;
-            for (int w = 0; w < kStepThreads / 64; ++w) t += wave_kept[w];
-            if (t) atomicAdd(a.cnt_out, t);
+    // one atomic per workgroup for each count: a counter taking one per wave
+    // and grid-stride turn (2.6e5 at 2^24 holes) serialised the whole step
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) pairs += __shfl_xor(pairs, m);
+    __shared__ uint32_t wave_kept[kStepThreads / 64];
+    __shared__ unsigned long long wave_pairs[kStepThreads / 64];
+    if (lane == 0) {
+        wave_kept[threadIdx.x >> 6] = kept;
+        wave_pairs[threadIdx.x >> 6] = pairs;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        unsigned long long pr = 0;
+        for (int w = 0; w < kStepThreads / 64; ++w) {
+            t += wave_kept[w];
+            pr += wave_pairs[w];
         }
+        if (t) atomicAdd(cnt_out, t);
+        if (pr && a.coulomb) atomicAdd(&a.stats[1], pr);
     }
 }
 
