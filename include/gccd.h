@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define GCCD_ABI_VERSION 3u
+#define GCCD_ABI_VERSION 4u
 
 enum {
     GCCD_OK = 0,
@@ -89,6 +89,8 @@ typedef struct {
     int64_t graph_replays;     /* 32-step HIP graphs replayed by gccd_run (schedule GRAPH) */
     int32_t schedule;          /* the GCCD_SCHEDULE_* in force                        */
     int32_t graph_usable;      /* 0 once a capture for this load was refused          */
+    int32_t tile_sources;      /* sources per staged tile of the Eq. (6) launches     */
+    int32_t reserved;          /* 0                                                   */
 } gccd_stats_t;
 
 /* Creates a context bound to the current HIP device and to hip_stream (a
@@ -187,18 +189,33 @@ int gccd_stats(gccd_ctx* c, gccd_stats_t* out);
  * GCCD_E_INVALID outside those ranges. */
 int gccd_set_launch(gccd_ctx* c, int32_t targets_per_thread, int32_t source_chunks);
 
-/* Picks the launch shape of gccd_set_launch by measurement: times the
- * Eq. (6) launch of the loaded state (its travelling holes against their
- * sources) for targets per thread 1, 2, 4 and source chunks 0 (automatic),
- * 4, 8, 12, 16, 20, 24, 28, 32, 36, 40, 48, 56, 64 (capped per event at its
- * tile count), the median of three launches each after one untimed, and
- * keeps the fastest for this load and later ones, as gccd_set_launch would.
- * About 170 launches: call
- * it once per workload.  The shape changes the FP32 summation order, so
- * results are reproducible across processes only for a fixed shape: the
- * chosen values (any pointer may be NULL) can be passed to gccd_set_launch.
- * Without Coulomb repulsion or travelling holes nothing is timed and the
- * current shape stays.  Synchronises the stream.  GCCD_E_STATE before load. */
+/* Sources per tile of the Eq. (6) work split (the paper's Sec. III.B
+ * kernel stages the sources through shared memory in blocks; here a work
+ * item sums its target block against a run of such tiles): 64, 128 or 256,
+ * or 0 for the automatic choice, which takes 64 when the load's work items
+ * at that size still fit in one round of workgroups (a small cloud: more,
+ * shorter items) and 256 otherwise.  Smaller tiles exist for one target per
+ * thread in the default precision; other shapes and precisions use 256
+ * whatever is set.  The tile size changes which tiles share a partial sum
+ * and so the FP32 summation order.  Applies to the current load and later
+ * ones; synchronises the stream.  GCCD_E_INVALID for any other value. */
+int gccd_set_tile(gccd_ctx* c, int32_t sources);
+
+/* Picks the launch shape of gccd_set_launch and gccd_set_tile by
+ * measurement: times the Eq. (6) launch of the loaded state (its travelling
+ * holes against their sources) for (targets per thread, tile sources) in
+ * (1, 64), (1, 128), (1, 256), (2, 256), (4, 256) (the first two in the
+ * default precision only) and source chunks 0 (automatic), 4, 8, 12, 16,
+ * 20, 24, 28, 32, 36, 40, 48, 56, 64 (capped per event at its tile count),
+ * the median of three launches each after one untimed, and keeps the
+ * fastest for this load and later ones, as those calls would.  About 280
+ * launches: call it once per workload.  The shape changes the FP32
+ * summation order, so results are reproducible across processes only for
+ * a fixed shape: the chosen values (any pointer may be NULL; the tile size
+ * is gccd_stats' tile_sources) can be passed to gccd_set_launch and
+ * gccd_set_tile.  Without Coulomb repulsion or travelling holes nothing is
+ * timed and the current shape stays.  Synchronises the stream.
+ * GCCD_E_STATE before load. */
 int gccd_autotune(gccd_ctx* c, int32_t* targets_per_thread, int32_t* source_chunks,
                   double* ms_per_launch);
 

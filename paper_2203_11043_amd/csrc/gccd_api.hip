@@ -117,6 +117,8 @@ struct gccd_ctx {
 
     int tpt_fixed = 0, chunks_fixed = 0;
     int tpt = 1;
+    int unit = kTile;       // sources per staged tile of the Eq. (6) launch (choose_unit)
+    int unit_fixed = 0;     // gccd_set_tile: 0 automatic
     int precision = GCCD_PRECISION_DEFAULT;
 
     // far-field closure (load-independent buffers)
@@ -338,7 +340,7 @@ void plan_tail(gccd_ctx* c, uint64_t cap) {
     uint64_t items = 0, big = 0;
     for (uint32_t e = 0; e < c->n_events; ++e) {
         const uint64_t ne = c->off_h[e + 1] - c->off_h[e];
-        const uint64_t tiles = (ne + kTile - 1) / kTile, s = (uint64_t)c->chunks_h[e];
+        const uint64_t tiles = (ne + c->unit - 1) / c->unit, s = (uint64_t)c->chunks_h[e];
         items += (ne + per - 1) / per * s;
         big = std::max<uint64_t>(big, (tiles + s - 1) / s);
     }
@@ -347,7 +349,7 @@ void plan_tail(gccd_ctx* c, uint64_t cap) {
     for (uint32_t e : c->order_h) {
         if (need <= 0) break;
         const uint64_t ne = c->off_h[e + 1] - c->off_h[e];
-        const uint64_t tiles = (ne + kTile - 1) / kTile, blocks = (ne + per - 1) / per;
+        const uint64_t tiles = (ne + c->unit - 1) / c->unit, blocks = (ne + per - 1) / per;
         const uint64_t s = (uint64_t)c->chunks_h[e];
         if ((tiles + s - 1) / s < 4) break;  // smaller events have short items already
         need -= event_tail(tiles, blocks, s, cap, need, &c->chunks_h[e], &c->tail_h[e],
@@ -355,10 +357,10 @@ void plan_tail(gccd_ctx* c, uint64_t cap) {
     }
 }
 
-// The automatic first-layer chunk count of an event of ne holes when the
-// load has tblocks target blocks in all.
-uint64_t auto_chunks(uint64_t ne, uint64_t tblocks, int n_cu, uint64_t cap) {
-    const uint64_t tiles = (ne + kTile - 1) / kTile;
+// The automatic first-layer chunk count of an event of ne holes in tiles of
+// `unit` sources when the load has tblocks target blocks in all.
+uint64_t auto_chunks(uint64_t ne, uint64_t unit, uint64_t tblocks, int n_cu, uint64_t cap) {
+    const uint64_t tiles = (ne + unit - 1) / unit;
     const uint64_t want = (uint64_t)n_cu * 64;
     uint64_t s = std::max<uint64_t>((ne + 3071) / 3072, (want + tblocks - 1) / tblocks);
     s = std::min<uint64_t>(s, std::max<uint64_t>(1, tiles));
@@ -366,7 +368,34 @@ uint64_t auto_chunks(uint64_t ne, uint64_t tblocks, int n_cu, uint64_t cap) {
     return balance_chunks(tiles, std::min<uint64_t>(s, cap), cap);
 }
 
+// Sources per staged tile of the one-target-per-thread default kernel:
+// automatically kTile / 4 when even one such tile per chunk gives every
+// target block's items a single round of workgroup slots (a small load,
+// whose time is the length of one item), else kTile; other shapes and
+// precisions always kTile.
+uint64_t auto_unit(uint64_t items_at_quarter_tiles, int n_cu, int slots_per_cu) {
+    return items_at_quarter_tiles <= (uint64_t)n_cu * (uint64_t)slots_per_cu ? kTile / 4 : kTile;
+}
+
+void choose_unit(gccd_ctx* c) {
+    if (c->tpt != 1 || c->precision != GCCD_PRECISION_DEFAULT) {
+        c->unit = kTile;
+        return;
+    }
+    if (c->unit_fixed) {
+        c->unit = c->unit_fixed;
+        return;
+    }
+    uint64_t items = 0;
+    for (uint32_t e = 0; e < c->n_events; ++e) {
+        const uint64_t ne = c->off_h[e + 1] - c->off_h[e];
+        items += (ne + kFieldThreads - 1) / kFieldThreads * ((ne + kTile / 4 - 1) / (kTile / 4));
+    }
+    c->unit = (int)auto_unit(items, c->n_cu, field_slots_per_cu(1, GCCD_PRECISION_DEFAULT));
+}
+
 void choose_chunks(gccd_ctx* c) {
+    choose_unit(c);
     uint64_t tblocks = 0;
     for (uint32_t e = 0; e < c->n_events; ++e)
         tblocks += (c->off_h[e + 1] - c->off_h[e] + kFieldThreads * c->tpt - 1) /
@@ -379,13 +408,13 @@ void choose_chunks(gccd_ctx* c) {
     const uint64_t cap = split ? kMaxChunks / 2 : kMaxChunks;
     for (uint32_t e = 0; e < c->n_events; ++e) {
         const uint64_t ne = c->off_h[e + 1] - c->off_h[e];
-        const uint64_t tiles = (ne + kTile - 1) / kTile;
+        const uint64_t tiles = (ne + c->unit - 1) / c->unit;
         uint64_t s;
         if (c->chunks_fixed) {
             // at most one chunk per tile: small events of a batch get no empty chunks
             s = std::min<uint64_t>((uint64_t)c->chunks_fixed, std::max<uint64_t>(1, tiles));
         } else {
-            s = auto_chunks(ne, tblocks, c->n_cu, cap);
+            s = auto_chunks(ne, (uint64_t)c->unit, tblocks, c->n_cu, cap);
         }
         s = std::min<uint64_t>(s, cap);
         c->chunks_h[e] = (int32_t)s;
@@ -549,6 +578,7 @@ FieldArgs field_args(const gccd_ctx* c, bool targets_all) {
     fa.n_items = c->sched + kSchedItems;
     fa.queue = c->sched + kSchedQueue;
     fa.near_compensated = c->near_compensated ? 1 : 0;
+    fa.unit = c->unit;
     const double eps2 = c->p.softening_um * c->p.softening_um;
     fa.acc2 = (float)((kExactRadius * kExactRadius + 1.0) * eps2);
     fa.acc_box2 = kExactRadius * kExactRadius * eps2;
@@ -1095,6 +1125,23 @@ int gccd_set_launch(gccd_ctx* c, int32_t tpt, int32_t chunks) {
     return GCCD_OK;
 }
 
+int gccd_set_tile(gccd_ctx* c, int32_t sources) {
+    if (!c) return GCCD_E_INVALID;
+    if (!(sources == 0 || sources == kTile / 4 || sources == kTile / 2 || sources == kTile))
+        return fail(c, GCCD_E_INVALID, "gccd_set_tile: sources must be 0, 64, 128 or 256");
+    c->unit_fixed = sources;
+    if (c->loaded) {
+        GCCD_HIP(c, hipStreamSynchronize(c->stream));
+        choose_chunks(c);
+        int r = size_chunk_buffers(c);
+        if (r != GCCD_OK) {
+            free_buffers(c);
+            return r;
+        }
+    }
+    return GCCD_OK;
+}
+
 int gccd_set_precision(gccd_ctx* c, int32_t mode) {
     if (!c) return GCCD_E_INVALID;
     if (mode < GCCD_PRECISION_DEFAULT || mode > GCCD_PRECISION_FP64)
@@ -1219,19 +1266,25 @@ int gccd_autotune(gccd_ctx* c, int32_t* targets_per_thread, int32_t* source_chun
     if (!c->loaded) return fail(c, GCCD_E_STATE, "gccd_autotune before gccd_load");
     GCCD_HIP(c, hipStreamSynchronize(c->stream));
     double best_ms = -1.0;
-    int best_t = c->tpt_fixed, best_s = c->chunks_fixed;
+    int best_t = c->tpt_fixed, best_s = c->chunks_fixed, best_u = c->unit_fixed;
     if (c->list_mode && c->n_active > 0) {
         hipEvent_t e0, e1;
         GCCD_HIP(c, hipEventCreate(&e0));
         GCCD_HIP(c, hipEventCreate(&e1));
-        static const int kT[3] = {1, 2, 4};
+        // (targets per thread, tile sources): smaller tiles exist for the
+        // one-target-per-thread default kernel only
+        static const int kTU[5][2] = {{1, kTile / 4}, {1, kTile / 2}, {1, kTile}, {2, kTile},
+                                      {4, kTile}};
         static const int kS[14] = {0, 4, 8, 12, 16, 20, 24, 28, 32, 36, 40, 48, 56, 64};
         int r = GCCD_OK;
-        for (int ti = 0; ti < 3 && r == GCCD_OK; ++ti)
+        for (int ti = 0; ti < 5 && r == GCCD_OK; ++ti) {
+            const int tpt = kTU[ti][0], unit = kTU[ti][1];
+            if (c->precision != GCCD_PRECISION_DEFAULT && unit != kTile) continue;
             for (int si = 0; si < 14 && r == GCCD_OK; ++si) {
-                c->tpt_fixed = kT[ti];
+                c->tpt_fixed = tpt;
                 c->chunks_fixed = kS[si];
-                c->tpt = kT[ti];
+                c->unit_fixed = unit;
+                c->tpt = tpt;
                 choose_chunks(c);
                 r = size_chunk_buffers(c);
                 if (r == GCCD_OK) r = build_items(c, c->host_active);
@@ -1252,10 +1305,12 @@ int gccd_autotune(gccd_ctx* c, int32_t* targets_per_thread, int32_t* source_chun
                 std::sort(t, t + 3);
                 if (best_ms < 0.0 || t[1] < best_ms) {
                     best_ms = t[1];
-                    best_t = kT[ti];
+                    best_t = tpt;
                     best_s = kS[si];
+                    best_u = unit;
                 }
             }
+        }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         // the timed launches left close-pair sums that nothing consumed
@@ -1271,6 +1326,7 @@ int gccd_autotune(gccd_ctx* c, int32_t* targets_per_thread, int32_t* source_chun
     // keep the fastest shape for this load and later ones
     c->tpt_fixed = best_t;
     c->chunks_fixed = best_s;
+    c->unit_fixed = best_u;
     c->tpt = best_t ? best_t : 1;
     choose_chunks(c);
     int r = size_chunk_buffers(c);
@@ -1594,6 +1650,7 @@ int gccd_stats(gccd_ctx* c, gccd_stats_t* out) {
     memset(out, 0, sizeof *out);
     out->targets_per_thread = c->tpt;
     out->source_chunks = c->loaded ? c->chunks_h[0] : 0;
+    out->tile_sources = c->loaded ? c->unit : 0;
     out->field_ms = c->field_ms;
     out->field_launches = c->field_launches;
     out->graph_replays = c->graph_replays;
@@ -1691,18 +1748,23 @@ int gccd_field_noalloc(const gccd_params* p, int64_t n, const double* x, const d
     hipStream_t st = (hipStream_t)hip_stream;
     const uint32_t nn = (uint32_t)n;
 
-    // the chunk plan of choose_chunks for one event, one target per thread
+    // the tile size and chunk plan of choose_unit and choose_chunks for one
+    // event, one target per thread; `tiles` counts the 256-source tiles whose
+    // boxes gather_tiles writes, `utiles` the tiles of the chosen size
     const uint64_t tiles = ((uint64_t)nn + kTile - 1) / kTile;
     const uint64_t blocks = ((uint64_t)nn + kFieldThreads - 1) / kFieldThreads;
+    const uint64_t unit =
+        auto_unit(blocks * (((uint64_t)nn + kTile / 4 - 1) / (kTile / 4)), d.n_cu, d.slots);
+    const uint64_t utiles = ((uint64_t)nn + unit - 1) / unit;
     const uint64_t cap = kMaxChunks;
-    int32_t g = (int32_t)std::min<uint64_t>(auto_chunks(nn, blocks, d.n_cu, cap), cap);
+    int32_t g = (int32_t)std::min<uint64_t>(auto_chunks(nn, unit, blocks, d.n_cu, cap), cap);
     int32_t tail = 0;
     uint32_t split = 0;
     {
         const uint64_t slots = (uint64_t)d.n_cu * (uint64_t)d.slots;
-        const uint64_t big = (tiles + g - 1) / (uint64_t)g;
+        const uint64_t big = (utiles + g - 1) / (uint64_t)g;
         if (blocks * (uint64_t)g < 32 * slots && big >= 4)
-            (void)event_tail(tiles, blocks, (uint64_t)g, cap, (int64_t)(slots * big / 2), &g,
+            (void)event_tail(utiles, blocks, (uint64_t)g, cap, (int64_t)(slots * big / 2), &g,
                              &tail, &split);
     }
     const uint32_t n_items = (uint32_t)(blocks * (uint64_t)g);
@@ -1784,6 +1846,7 @@ int gccd_field_noalloc(const gccd_params* p, int64_t n, const double* x, const d
     fa.acc_box2 = kExactRadius * kExactRadius * eps2;
     fa.acc_scale = std::ldexp(eps2, kExactShift);
     fa.close = close;
+    fa.unit = (int32_t)unit;
     NA_HIP(launch_field(fa, 1, GCCD_PRECISION_DEFAULT, n_items, 0u, st));
     const double K = kQ / (4.0 * kPi * kEps0 * p->eps_r) * 1e12 * 1e-2;
     NA_HIP(launch_field_finish(part, nn, ev_chunks, 0, 0, keys0, ev_off, kl, nn, K, close,

@@ -69,6 +69,9 @@ struct FieldArgs {
     uint32_t* queue;            // persistent launch: [0] next item (zero before the launch)
     int32_t near_compensated;   // one target per thread, default precision: tiles within
                                 // rho/4 take the compensated difference (small launches)
+    int32_t unit;               // sources per staged tile of the one-target-per-thread
+                                // default kernel: kTile, kTile / 2 or kTile / 4 (the
+                                // items count tiles of that size; other kernels: kTile)
     // Close pairs summed exactly (default precision): a pair with r^2 + eps^2 below
     // acc2 has its term formed in FP64 and added, in fixed point, to the target's
     // slot of `close` ([3][pstride] 64-bit integers, zero before the launch; the

@@ -767,7 +767,26 @@ struct ExpandedLds {
 // every wave finds a close pair in such tiles, the branch is taken almost
 // always, and the branch-free form halves the launch; in a full GPU the
 // check is cheaper per pair.
-template <bool COMP>
+// The box bound k (0-2 low x, y, z; 3-5 high) of source tile t of UNIT
+// sources of the event whose 256-source tiles start at tile0: a 256-source
+// tile's own box, a 64-source quarter's, or the union of two quarters'.
+template <int UNIT>
+__device__ __forceinline__ double unit_bound(const FieldArgs& a, uint32_t tile0, uint32_t t,
+                                             int k) {
+    const size_t st = a.tile_stride;
+    if (UNIT == kTile) return a.tile_box[(size_t)k * st + tile0 + t];
+    if (UNIT == kTile / 4)
+        return a.tile_box[(size_t)(6 + 4 * k + (int)(t & 3u)) * st + tile0 + (t >> 2)];
+    const int q = 2 * (int)(t & 1u);
+    const double v0 = a.tile_box[(size_t)(6 + 4 * k + q) * st + tile0 + (t >> 1)];
+    const double v1 = a.tile_box[(size_t)(6 + 4 * k + q + 1) * st + tile0 + (t >> 1)];
+    return k < 3 ? fmin(v0, v1) : fmax(v0, v1);
+}
+
+// UNIT: sources per staged tile (256, 128 or 64; the work item's first,
+// step and end count such tiles).  Smaller tiles give a small cloud more
+// work items of fewer sources each; the LDS layout is the same.
+template <bool COMP, int UNIT>
 __device__ __forceinline__ void expanded_item(const FieldArgs& a, const FieldItem it,
                                               ExpandedLds& L) {
     auto& sh = L.sh;
@@ -780,7 +799,7 @@ __device__ __forceinline__ void expanded_item(const FieldArgs& a, const FieldIte
     const uint32_t ns = a.sources_all ? ne : na;
     const uint32_t tbase = it.blk * (uint32_t)kFieldThreads;
     if (tbase >= nt) return;  // the whole workgroup leaves before any barrier
-    const uint32_t ntiles = (ns + kTile - 1) / kTile;
+    const uint32_t ntiles = (ns + UNIT - 1) / UNIT;
     const uint32_t tile0 = a.ev_tile[it.event];
     const uint32_t chunk = it.group;  // partial-sum group written
     const uint32_t step_t = it.step;
@@ -866,16 +885,16 @@ __device__ __forceinline__ void expanded_item(const FieldArgs& a, const FieldIte
     double qx = 0.0, qy = 0.0, qz = 0.0;  // this lane's source of the next tile
     double qb = 0.0;                      // lanes 0-5: one bound of that tile's box
     auto fetch = [&](uint32_t t) {
-        const uint32_t i = t * kTile + (uint32_t)tid;
+        const uint32_t i = t * UNIT + (uint32_t)tid;
         qx = ox;
         qy = oy;
         qz = oz;
-        if (i < ns) {
+        if (tid < UNIT && i < ns) {
             qx = a.px[off + i];
             qy = a.py[off + i];
             qz = a.pz[off + i];
         }
-        if (tid < 6) qb = a.tile_box[(size_t)tid * a.tile_stride + tile0 + t];
+        if (tid < 6) qb = unit_bound<UNIT>(a, tile0, t, tid);
     };
     auto stage = [&](int b) {
         if (tid < 6) tbox[b][tid] = qb;
@@ -899,7 +918,7 @@ __device__ __forceinline__ void expanded_item(const FieldArgs& a, const FieldIte
     for (uint32_t t = t_first; t < t_end; t += step_t) {
         const uint32_t next = t + step_t;
         if (next < t_end) fetch(next);
-        const uint32_t cnt = min((uint32_t)kTile, ns - t * kTile);
+        const uint32_t cnt = min((uint32_t)UNIT, ns - t * UNIT);
         const float* mxp = sh[buf][0];
         const float* myp = sh[buf][1];
         const float* mzp = sh[buf][2];
@@ -931,13 +950,13 @@ __device__ __forceinline__ void expanded_item(const FieldArgs& a, const FieldIte
         } else {
             float bx = 0.0f, by = 0.0f, bz = 0.0f;
             if (g2 >= rc2d)
-                diff_tile<false>(a, L.xl, t * kTile, mxp, myp, mzp, sh[buf][4], sh[buf][5], sh[buf][6], cnt,
+                diff_tile<false>(a, L.xl, t * UNIT, mxp, myp, mzp, sh[buf][4], sh[buf][5], sh[buf][6], cnt,
                                  thx, thy, thz, tlx, tly, tlz, a.eps2, rc2, bx, by, bz);
             else if (COMP)
-                comp_tile(a, L.xl, t * kTile, mxp, myp, mzp, sh[buf][4], sh[buf][5], sh[buf][6], cnt, thx,
+                comp_tile(a, L.xl, t * UNIT, mxp, myp, mzp, sh[buf][4], sh[buf][5], sh[buf][6], cnt, thx,
                           thy, thz, tlx, tly, tlz, a.eps2, rc2, bx, by, bz);
             else
-                diff_tile<true>(a, L.xl, t * kTile, mxp, myp, mzp, sh[buf][4], sh[buf][5], sh[buf][6], cnt,
+                diff_tile<true>(a, L.xl, t * UNIT, mxp, myp, mzp, sh[buf][4], sh[buf][5], sh[buf][6], cnt,
                                 thx, thy, thz, tlx, tly, tlz, a.eps2, rc2, bx, by, bz);
             ex += bx;
             ey += by;
@@ -961,11 +980,11 @@ __device__ __forceinline__ void expanded_item(const FieldArgs& a, const FieldIte
 }
 
 // One workgroup per work item.
-template <bool COMP>
+template <bool COMP, int UNIT>
 __global__ __launch_bounds__(kFieldThreads) void field_tiles_expanded(FieldArgs a) {
     __shared__ __align__(16) ExpandedLds L;
     if (threadIdx.x == 0) L.xl.n = 0;  // ordered before any push by the item's first barrier
-    expanded_item<COMP>(a, a.items[blockIdx.x], L);
+    expanded_item<COMP, UNIT>(a, a.items[blockIdx.x], L);
 }
 
 // Persistent form: a fixed grid of workgroups takes the items in list order
@@ -973,7 +992,7 @@ __global__ __launch_bounds__(kFieldThreads) void field_tiles_expanded(FieldArgs 
 // Every workgroup leaves once the counter has passed the end, so the grid
 // drains whatever the item count; the grid and the arguments stay the same
 // when the items are rebuilt, which lets a captured graph be replayed.
-template <bool COMP>
+template <bool COMP, int UNIT>
 __global__ __launch_bounds__(kFieldThreads) __attribute__((amdgpu_waves_per_eu(7)))
 void field_queue_expanded(FieldArgs a) {
     __shared__ __align__(16) ExpandedLds L;
@@ -986,7 +1005,7 @@ void field_queue_expanded(FieldArgs a) {
         const uint32_t i = next;
         __syncthreads();  // every lane has read `next` before lane 0 writes it again
         if (i >= n_items) break;
-        expanded_item<COMP>(a, a.items[i], L);
+        expanded_item<COMP, UNIT>(a, a.items[i], L);
     }
 }
 
@@ -1352,7 +1371,8 @@ static hipError_t launch_field_prec(const FieldArgs& a, int tpt, uint32_t n_item
 int field_queue_slots_per_cu() {
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &n, reinterpret_cast<const void*>(field_queue_expanded<false>), kFieldThreads, 0) !=
+            &n, reinterpret_cast<const void*>(field_queue_expanded<false, kTile>), kFieldThreads,
+            0) !=
         hipSuccess) {
         (void)hipGetLastError();
         return 1;
@@ -1375,7 +1395,7 @@ int field_slots_per_cu(int tpt, int precision) {
                 &n, reinterpret_cast<const void*>(field_tiles_f64<4>), kFieldThreads, 0);
     } else if (tpt == 1 && precision == GCCD_PRECISION_DEFAULT) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &n, reinterpret_cast<const void*>(field_tiles_expanded<false>), kFieldThreads, 0);
+            &n, reinterpret_cast<const void*>(field_tiles_expanded<false, kTile>), kFieldThreads, 0);
     } else if (tpt == 1) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
             &n, reinterpret_cast<const void*>(field_tiles<1, GCCD_PRECISION_BLOCK>),
@@ -1402,20 +1422,47 @@ hipError_t launch_field(const FieldArgs& a, int tpt, int precision, uint32_t n_i
         // the item count is read on the device: launched even with none
         const hipError_t e = launch_fill_u32(a.queue, 1u, 0u, s);
         if (e != hipSuccess) return e;
-        if (a.near_compensated)
-            field_queue_expanded<true><<<queue_grid, kFieldThreads, 0, s>>>(a);
-        else
-            field_queue_expanded<false><<<queue_grid, kFieldThreads, 0, s>>>(a);
+        const bool c = a.near_compensated != 0;
+        switch (a.unit) {
+            case kTile / 4:
+                if (c) field_queue_expanded<true, kTile / 4><<<queue_grid, kFieldThreads, 0, s>>>(a);
+                else field_queue_expanded<false, kTile / 4><<<queue_grid, kFieldThreads, 0, s>>>(a);
+                break;
+            case kTile / 2:
+                if (c) field_queue_expanded<true, kTile / 2><<<queue_grid, kFieldThreads, 0, s>>>(a);
+                else field_queue_expanded<false, kTile / 2><<<queue_grid, kFieldThreads, 0, s>>>(a);
+                break;
+            case kTile:
+                if (c) field_queue_expanded<true, kTile><<<queue_grid, kFieldThreads, 0, s>>>(a);
+                else field_queue_expanded<false, kTile><<<queue_grid, kFieldThreads, 0, s>>>(a);
+                break;
+            default: return hipErrorInvalidValue;
+        }
         return hipGetLastError();
     }
     if (n_items == 0) return hipSuccess;
+    // only the one-target-per-lane default kernel takes smaller tiles
+    if (a.unit != kTile && !(tpt == 1 && precision == GCCD_PRECISION_DEFAULT))
+        return hipErrorInvalidValue;
     switch (precision) {
         case GCCD_PRECISION_DEFAULT:
             if (tpt == 1) {
-                if (a.near_compensated)
-                    field_tiles_expanded<true><<<n_items, kFieldThreads, 0, s>>>(a);
-                else
-                    field_tiles_expanded<false><<<n_items, kFieldThreads, 0, s>>>(a);
+                const bool c = a.near_compensated != 0;
+                switch (a.unit) {
+                    case kTile / 4:
+                        if (c) field_tiles_expanded<true, kTile / 4><<<n_items, kFieldThreads, 0, s>>>(a);
+                        else field_tiles_expanded<false, kTile / 4><<<n_items, kFieldThreads, 0, s>>>(a);
+                        break;
+                    case kTile / 2:
+                        if (c) field_tiles_expanded<true, kTile / 2><<<n_items, kFieldThreads, 0, s>>>(a);
+                        else field_tiles_expanded<false, kTile / 2><<<n_items, kFieldThreads, 0, s>>>(a);
+                        break;
+                    case kTile:
+                        if (c) field_tiles_expanded<true, kTile><<<n_items, kFieldThreads, 0, s>>>(a);
+                        else field_tiles_expanded<false, kTile><<<n_items, kFieldThreads, 0, s>>>(a);
+                        break;
+                    default: return hipErrorInvalidValue;
+                }
                 return hipGetLastError();
             }
             return launch_field_prec<GCCD_PRECISION_DEFAULT>(a, tpt, n_items, s);

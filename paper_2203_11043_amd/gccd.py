@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 # GCCD_LIB selects another build of the same library (the tests point it at the
 # host-sanitized variant)
 LIB_PATH = os.environ.get("GCCD_LIB") or os.path.join(_HERE, "libgccd.so")
-ABI_VERSION = 3
+ABI_VERSION = 4
 CLOSURE_WEIGHTS = 290784      # GCCD_CLOSURE_WEIGHTS
 GCCD_NOALLOC_MAX_CARRIERS = 32768   # largest load of gccd_field_noalloc
 
@@ -43,6 +43,7 @@ EXPORTS = ("gccd_init", "gccd_load", "gccd_load_events", "gccd_run", "gccd_image
            "gccd_image_events", "gccd_field", "gccd_positions", "gccd_stats",
            "gccd_set_launch", "gccd_autotune", "gccd_set_precision", "gccd_set_closure",
            "gccd_closure_parts", "gccd_set_timing", "gccd_set_schedule", "gccd_field_noalloc",
+           "gccd_set_tile",
            "gccd_strerror", "gccd_last_error", "gccd_destroy")
 
 
@@ -85,6 +86,8 @@ class CStats(ctypes.Structure):
         ("graph_replays", ctypes.c_int64),
         ("schedule", ctypes.c_int32),
         ("graph_usable", ctypes.c_int32),
+        ("tile_sources", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -104,6 +107,7 @@ def _load():
     L.gccd_positions.argtypes = [P, P, P, P, P]
     L.gccd_stats.argtypes = [P, ctypes.POINTER(CStats)]
     L.gccd_set_launch.argtypes = [P, i32, i32]
+    L.gccd_set_tile.argtypes = [P, i32]
     L.gccd_set_precision.argtypes = [P, i32]
     L.gccd_autotune.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                 ctypes.POINTER(d)]
@@ -313,6 +317,12 @@ def gccd_stats(ctx: int) -> dict:
 
 def gccd_set_launch(ctx: int, targets_per_thread: int = 0, source_chunks: int = 0) -> None:
     _check(ctx, lib.gccd_set_launch(ctx, int(targets_per_thread), int(source_chunks)))
+
+
+def gccd_set_tile(ctx: int, sources: int = 0) -> None:
+    """Sources per staged tile of the Eq. (6) work split: 64, 128, 256 or 0
+    (automatic)."""
+    _check(ctx, lib.gccd_set_tile(ctx, int(sources)))
 
 
 def gccd_autotune(ctx: int):

@@ -29,7 +29,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported(g):
     names = declared_functions()
-    assert len(names) == 20
+    assert len(names) == 21
     for name in names:
         assert hasattr(g.lib, name), name
     assert sorted(g.EXPORTS) == names
@@ -48,6 +48,7 @@ def test_struct_layout_matches_header(g, tmp_path):
         " offsetof(gccd_stats_t, source_chunks), offsetof(gccd_stats_t, max_source_chunks),"
         " offsetof(gccd_stats_t, near_chunks), offsetof(gccd_stats_t, graph_replays),"
         " offsetof(gccd_stats_t, graph_usable), GCCD_CLOSURE_WEIGHTS);"
+        'printf("%zu\\n", offsetof(gccd_stats_t, tile_sources));'
         'printf("%d\\n", GCCD_NOALLOC_MAX_CARRIERS);'
         "\nreturn 0;}\n")
     exe = tmp_path / "layout"
@@ -58,7 +59,8 @@ def test_struct_layout_matches_header(g, tmp_path):
     want = [ctypes.sizeof(P), P.thickness_um.offset, P.coulomb.offset, P.seed.offset,
             P.event.offset, ctypes.sizeof(S), S.field_ms.offset, S.source_chunks.offset,
             S.max_source_chunks.offset, S.near_chunks.offset, S.graph_replays.offset,
-            S.graph_usable.offset, g.CLOSURE_WEIGHTS, g.GCCD_NOALLOC_MAX_CARRIERS]
+            S.graph_usable.offset, g.CLOSURE_WEIGHTS, S.tile_sources.offset,
+            g.GCCD_NOALLOC_MAX_CARRIERS]
     assert list(map(int, out)) == want
 
 
@@ -107,6 +109,7 @@ def test_null_arguments(g):
     assert L.gccd_positions(None, None, None, None, None) == g.GCCD_E_INVALID
     assert L.gccd_stats(None, None) == g.GCCD_E_INVALID
     assert L.gccd_set_launch(None, 0, 0) == g.GCCD_E_INVALID
+    assert L.gccd_set_tile(None, 0) == g.GCCD_E_INVALID
     assert L.gccd_set_timing(None, 1) == g.GCCD_E_INVALID
     assert L.gccd_set_precision(None, 0) == g.GCCD_E_INVALID
     assert L.gccd_set_schedule(None, 2) == g.GCCD_E_INVALID

@@ -103,9 +103,11 @@ def test_field_ragged_launch_shapes(g, W, orc, tpt, chunks):
     ea, er = field_errors(E, Eo, A)
     report(f"cloud n=5003 tpt={st['targets_per_thread']} chunks={st['source_chunks']}", ea, er)
     assert ea <= FIELD_TOL and er <= FIELD_TOL
-    if tpt:   # a fixed chunk count is capped at the event's 256-source tiles
+    if tpt:   # a fixed chunk count is capped at the event's tiles (of the size in force)
+        unit = st["tile_sources"]
         assert st["targets_per_thread"] == tpt
-        assert st["source_chunks"] == min(chunks, (5003 + 255) // 256)
+        assert unit in ((64, 128, 256) if tpt == 1 else (256,))
+        assert st["source_chunks"] == min(chunks, (5003 + unit - 1) // unit)
 
 
 @pytest.mark.parametrize("n", [30000, 100000, 300000])

@@ -107,6 +107,7 @@ def test_fp64_mode_matches_oracle(g, W, orc, tpt, chunks):
     assert ea <= FP64_TOL
     if chunks:   # FP64 takes at most 32 chunks, and no event more chunks than tiles
         assert st["source_chunks"] == min(chunks, 32, (5003 + 255) // 256)
+    assert st["tile_sources"] == 256
 
 
 def test_fp64_mode_track_and_batch(g, W, orc):
