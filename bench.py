@@ -288,8 +288,8 @@ def main() -> int:
                     help="one gccd_run call and one image per time step (a host round trip "
                          "per step) instead of one call for all timed steps")
     ap.add_argument("--no-autotune", action="store_true",
-                    help="batch workload: keep the automatic launch shape instead of "
-                         "measuring the candidates first (gccd_autotune)")
+                    help="keep the automatic launch shape instead of measuring the "
+                         "candidates first (gccd_autotune)")
     ap.add_argument("--no-closure", action="store_true",
                     help="skip the closure-versus-exact leg on the 1e6-hole cloud")
     ap.add_argument("--schedule", choices=("grid", "queue", "graph"), default="grid",
@@ -373,8 +373,6 @@ def main() -> int:
     tuned = None
     if args.workload == "batch":
         gccd.gccd_load_events(ctx, offsets, *xs)
-        if not args.no_autotune and not (args.tpt or args.chunks):
-            tuned = gccd.gccd_autotune(ctx)
 
         def image():
             gccd.gccd_image_events(ctx, args.events, 0.0, 0.0, w.pitch_um, w.nx, w.ny)
@@ -385,6 +383,8 @@ def main() -> int:
 
         def image():
             gccd.gccd_image(ctx, 0.0, 0.0, w.pitch_um, w.nx, w.ny, counts, nout)
+    if not args.no_autotune and not (args.tpt or args.chunks):
+        tuned = gccd.gccd_autotune(ctx)
 
     def run(k):
         """k time steps, as the library is used: one gccd_run call (counts
@@ -471,10 +471,12 @@ def main() -> int:
                       "then the image"),
             "positions": "f64",
             "pair_arithmetic": ("f32, origin per workgroup; far tiles in the expanded-square form, "
-                                "pairs closer than rho/4 with double-single differences"
+                                "pairs closer than rho/4 with double-single differences, pairs "
+                                "within 64 softening lengths in f64"
                                 if s1["targets_per_thread"] == 1 else
                                 "f32, origin per workgroup; pairs closer than rho/4 with "
-                                "double-single differences"),
+                                "double-single differences, pairs within 64 softening lengths "
+                                "in f64"),
             "targets_per_thread": s1["targets_per_thread"],
             "source_chunks": s1["source_chunks"],
             "max_source_chunks": s1["max_source_chunks"],
@@ -482,9 +484,11 @@ def main() -> int:
                          "HIP events), see graph_pass for the replayed graphs"
                          if args.schedule == "graph" else args.schedule),
             "graph_pass": graph_pass,
-            "launch_shape": ("autotuned: targets per thread %d, source chunks %s (%.2f ms)"
-                             % (tuned[0], tuned[1] or "automatic", tuned[2])) if tuned else
-                            ("fixed" if (args.tpt or args.chunks) else "automatic"),
+            "tile_sources": s1["tile_sources"],
+            "launch_shape": ("autotuned: targets per thread %d, source chunks %s, tile %d "
+                             "sources (%.3f ms)" % (tuned[0], tuned[1] or "automatic",
+                                                    s1["tile_sources"], tuned[2]))
+                            if tuned else ("fixed" if (args.tpt or args.chunks) else "automatic"),
         },
         "carrier_steps_per_s": csteps / elapsed,
         "pct_fp32_peak": 100.0 * FLOP_PER_PAIR * pair_rate / (PEAK_FP32_TFLOPS * 1e12),

@@ -43,6 +43,7 @@ enum : int {
     kSchedQueue = 0,  // persistent launch: next work item
     kSchedItems = 1,  // persistent launch: work items in the list
     kSchedStep = 2,   // list mode: step index of the first step of the current stretch
+    kSchedArrive = 3, // a small load's step kernel: its workgroups arrived (zero between)
     kSchedWords = 4
 };
 
@@ -1414,9 +1415,26 @@ int gccd_run(gccd_ctx* c, double dt_ps, int64_t max_steps, int64_t* steps_done,
     sa.stats = reinterpret_cast<unsigned long long*>(c->meta + kMetaStats);
     sa.misc = reinterpret_cast<int32_t*>(c->meta + kMetaFlag);
 
-    // Exact steps with every hole a source are pipelined (see gccd_ctx::keys);
+    // A small load's step kernel rebuilds the list itself (its last
+    // workgroup sorts, counts and gathers: two launches per step).  Other
+    // exact steps with every hole a source are pipelined (see gccd_ctx::keys);
     // the others need the list of the positions they run over.
-    const bool pipelined = c->list_mode && !use_closure && c->p.collected_are_sources;
+    const bool fused = c->list_mode && !use_closure && n <= (uint32_t)kFusedList &&
+                       c->n_tiles <= (uint32_t)kFusedTiles;
+    const bool pipelined =
+        !fused && c->list_mode && !use_closure && c->p.collected_are_sources;
+    if (fused) {
+        sa.arrive = c->sched + kSchedArrive;
+        sa.n_events = c->n_events;
+        sa.ev_tile = c->ev_tile_d;
+        sa.tile_event = c->tile_event_d;
+        sa.n_tiles = c->n_tiles;
+        sa.px = c->ps[0];
+        sa.py = c->ps[1];
+        sa.pz = c->ps[2];
+        sa.tile_box = c->tile_box;
+        sa.box_stride = std::max<uint32_t>(c->n_tiles, 1);
+    }
     if (c->list_mode && !pipelined) {
         int r = settle(c);
         if (r != GCCD_OK) return r;
@@ -1467,7 +1485,12 @@ int gccd_run(gccd_ctx* c, double dt_ps, int64_t max_steps, int64_t* steps_done,
             sa.keys_in = c->keys[c->cur];
             sa.keys_out = c->ukeys[c->u];
             sa.ev_active = c->ev_active_d[c->cur];
+            if (fused) {  // the kernel leaves the next step's list in place of this one's
+                sa.keys_sorted = c->keys[c->cur];
+                sa.ev_active_out = c->ev_active_d[c->cur];
+            }
             GCCD_HIP(c, launch_step(sa, n, c->stream));
+            if (fused) return GCCD_OK;
             if (!pipelined) return finish_list(c, c->ukeys[c->u]);  // the next step's list
             // The list of the new positions is sorted on the side stream while
             // the next step runs over the one the side stream finished last

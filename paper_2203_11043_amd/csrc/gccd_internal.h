@@ -13,6 +13,8 @@ constexpr int kBoxRows = 126;        // per source tile: its box (rows 0-5), its
                                      // quarters' boxes (row 6 + 4 k + q for bound k of quarter
                                      // q), its sixteen 16-slot groups' boxes (row 30 + 16 k + g)
 constexpr int kStepThreads = 256;
+constexpr int kFusedList = 2048;     // largest load whose step kernel rebuilds the list itself
+constexpr int kFusedTiles = 16;      // ... in at most this many source tiles
 
 // Carrier lists hold one 64-bit key per carrier:
 //   [event | collected | 36-bit Hilbert index of the 0.25 um cell | local index]
@@ -129,6 +131,24 @@ struct StepArgs {
     double close_unit;          // um^-2 per fixed-point unit of close
     unsigned long long* stats;  // [0] carrier-steps, [1] pair interactions
     int32_t* misc;              // [0] non-finite flag, [1] step after the last busy one
+    // A load of at most kFusedList carriers in at most kFusedTiles source
+    // tiles (list mode): with arrive set, the
+    // last workgroup of the step sorts keys_out into keys_sorted, writes each
+    // event's travelling holes to ev_active_out and gathers the positions and
+    // boxes of the n_tiles source tiles into px, py, pz, tile_box (what
+    // sort_keys, count_active and gather_tiles do for larger loads).
+    uint32_t* arrive;           // workgroups arrived ([1], zero between launches)
+    uint64_t* keys_sorted;
+    uint32_t* ev_active_out;
+    uint32_t n_events;
+    const uint32_t* ev_tile;
+    const uint32_t* tile_event;
+    uint32_t n_tiles;
+    double* px;
+    double* py;
+    double* pz;
+    double* tile_box;
+    uint32_t box_stride;
 };
 
 // precision: a GCCD_PRECISION_* mode

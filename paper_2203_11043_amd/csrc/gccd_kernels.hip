@@ -9,6 +9,7 @@
 // keeps them apart through the per-event slot offsets.
 #include "gccd.h"
 #include "gccd_internal.h"
+#include "gccd_sort_dev.h"
 
 #include <math.h>
 
@@ -1546,31 +1547,33 @@ hipError_t launch_count(const uint64_t* keys, const uint32_t* ev_off, uint32_t n
     return hipGetLastError();
 }
 
-// One workgroup per source tile g of event e = tile_event[g] (local tile
-// t = g - ev_tile[e]): positions of every slot of the tile, bounding box of
+// Source tile g of event e = tile_event[g] (local tile t = g - ev_tile[e]),
+// by one workgroup of kTile threads: positions of every slot of the tile
+// (key_at(slot) gives the slot's key; ns_or_active is the event's travelling
+// holes, the sources unless sources_all), bounding box of
 // the slots that are sources (rows 0-5 of box: low x, y, z, high x, y, z),
 // and the same for each 64-slot quarter of the tile (row 6 + 4 k + q for
 // bound k of quarter q) and each 16-slot group (row 30 + 16 k + g), which
 // the near-field kernel culls by.  The group boxes are the first four steps
 // of the lane reduction that gives the quarter boxes.
-__global__ __launch_bounds__(kTile) void gather_tiles(
-    const uint64_t* keys, const uint32_t* ev_off, const uint32_t* ev_tile,
-    const uint32_t* tile_event, const uint32_t* ev_active, int sources_all, KeyLayout kl,
-    const double* x, const double* y, const double* z, double* px, double* py, double* pz,
-    double* box, uint32_t stride) {
-    __shared__ double red[6][kTile / 64];
-    const uint32_t g = blockIdx.x;
+template <class KeyAt>
+__device__ __forceinline__ void gather_tile(uint32_t g, KeyAt key_at, const uint32_t* ev_off,
+                                            const uint32_t* ev_tile, const uint32_t* tile_event,
+                                            uint32_t ns_or_active, int sources_all, KeyLayout kl,
+                                            const double* x, const double* y, const double* z,
+                                            double* px, double* py, double* pz, double* box,
+                                            uint32_t stride, double (*red)[kTile / 64]) {
     const uint32_t e = tile_event[g];
     const uint32_t t = g - ev_tile[e];
     const uint32_t off = ev_off[e], ne = ev_off[e + 1] - off;
-    const uint32_t ns = sources_all ? ne : ev_active[e];
+    const uint32_t ns = sources_all ? ne : ns_or_active;
     const uint32_t i = t * kTile + threadIdx.x;
     double lx = INFINITY, ly = INFINITY, lz = INFINITY;
     double hx = -INFINITY, hy = -INFINITY, hz = -INFINITY;
     if (i < ne) {
         // a slot of event e holds a key of event e; the clamp keeps every
         // load inside the event regardless
-        const uint32_t c = off + min(key_local(keys[off + i], kl), ne - 1u);
+        const uint32_t c = off + min(key_local(key_at(off + i), kl), ne - 1u);
         const double vx = x[c], vy = y[c], vz = z[c];
         px[off + i] = vx;
         py[off + i] = vy;
@@ -1628,6 +1631,19 @@ __global__ __launch_bounds__(kTile) void gather_tiles(
     }
 }
 
+__global__ __launch_bounds__(kTile) void gather_tiles(
+    const uint64_t* keys, const uint32_t* ev_off, const uint32_t* ev_tile,
+    const uint32_t* tile_event, const uint32_t* ev_active, int sources_all, KeyLayout kl,
+    const double* x, const double* y, const double* z, double* px, double* py, double* pz,
+    double* box, uint32_t stride) {
+    __shared__ double red[6][kTile / 64];
+    const uint32_t g = blockIdx.x;
+    gather_tile(
+        g, [&](uint32_t slot) { return keys[slot]; }, ev_off, ev_tile, tile_event,
+        sources_all ? 0u : ev_active[tile_event[g]], sources_all, kl, x, y, z, px, py, pz, box,
+        stride, red);
+}
+
 hipError_t launch_gather(const uint64_t* keys, const uint32_t* ev_off, const uint32_t* ev_tile,
                          const uint32_t* tile_event, const uint32_t* ev_active, int sources_all,
                          uint32_t n_tiles, KeyLayout kl, const double* x, const double* y,
@@ -1681,6 +1697,121 @@ __device__ __forceinline__ double unit_open(uint32_t w) {
 //   carrier mode: one thread per carrier; travelling holes are counted, one
 //     atomic per wave.
 // ---------------------------------------------------------------------------
+// The list of a load of at most kFusedList carriers in at most kFusedTiles
+// source tiles, rebuilt by the last workgroup of its step: the new keys
+// sorted in LDS (bitonic_sort_lanes), each event's travelling holes (its
+// first collected key, by binary search in LDS), and the positions and
+// boxes of every source tile in slot order -- the same list, counts, slots
+// and boxes as sort_keys, count_active and gather_tiles.  Wave w gathers
+// quarter w of every tile, four tiles at a time with all their loads in
+// flight together; the tile boxes are reduced from the quarters' in LDS.
+__device__ __forceinline__ void build_small_list(const StepArgs& a) {
+    __shared__ uint64_t s[kFusedList + kFusedList / kSortItems];
+    __shared__ uint32_t act[kFusedList];
+    __shared__ double qbox[kFusedTiles][4][6];
+    const uint32_t n = a.n_all;
+    if (n <= (uint32_t)kFusedList / 2)
+        bitonic_sort_lanes<kFusedList / 2 / kStepThreads>(a.keys_out, n, s);
+    else
+        bitonic_sort_lanes<kFusedList / kStepThreads>(a.keys_out, n, s);
+    for (uint32_t i = threadIdx.x; i < n; i += kStepThreads) a.keys_sorted[i] = s[lds_slot(i)];
+    for (uint32_t e = threadIdx.x; e < a.n_events; e += kStepThreads) {
+        const uint32_t off = a.ev_off[e], ne = a.ev_off[e + 1] - off;
+        uint32_t lo = 0, hi = ne;  // first collected key of the segment in [lo, hi]
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (key_collected(s[lds_slot(off + mid)], a.kl))
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+        act[e] = lo;
+        a.ev_active_out[e] = lo;
+    }
+    __syncthreads();
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const size_t st = a.box_stride;
+    constexpr uint32_t kBatch = 4;
+    for (uint32_t g0 = 0; g0 < a.n_tiles; g0 += kBatch) {
+        double vx[kBatch], vy[kBatch], vz[kBatch];
+        bool src[kBatch];
+#pragma unroll
+        for (uint32_t b = 0; b < kBatch; ++b) {
+            vx[b] = vy[b] = vz[b] = 0.0;
+            src[b] = false;
+            const uint32_t g = g0 + b;
+            if (g < a.n_tiles) {
+                const uint32_t e = a.tile_event[g];
+                const uint32_t off = a.ev_off[e], ne = a.ev_off[e + 1] - off;
+                const uint32_t ns = a.sources_all ? ne : act[e];
+                const uint32_t i = (g - a.ev_tile[e]) * kTile + wave * 64u + lane;
+                if (i < ne) {
+                    const uint32_t c = off + min(key_local(s[lds_slot(off + i)], a.kl), ne - 1u);
+                    vx[b] = a.x[c];
+                    vy[b] = a.y[c];
+                    vz[b] = a.z[c];
+                    a.px[off + i] = vx[b];
+                    a.py[off + i] = vy[b];
+                    a.pz[off + i] = vz[b];
+                    src[b] = i < ns;
+                }
+            }
+        }
+#pragma unroll
+        for (uint32_t b = 0; b < kBatch; ++b) {
+            const uint32_t g = g0 + b;
+            if (g >= a.n_tiles) break;  // uniform
+            double lx = INFINITY, ly = INFINITY, lz = INFINITY;
+            double hx = -INFINITY, hy = -INFINITY, hz = -INFINITY;
+            if (src[b]) {
+                lx = hx = vx[b];
+                ly = hy = vy[b];
+                lz = hz = vz[b];
+            }
+#pragma unroll
+            for (int m = 1; m <= 8; m <<= 1) {
+                lx = fmin(lx, __shfl_xor(lx, m));
+                ly = fmin(ly, __shfl_xor(ly, m));
+                lz = fmin(lz, __shfl_xor(lz, m));
+                hx = fmax(hx, __shfl_xor(hx, m));
+                hy = fmax(hy, __shfl_xor(hy, m));
+                hz = fmax(hz, __shfl_xor(hz, m));
+            }
+            if ((lane & 15u) == 0) {
+                const uint32_t grp = wave * 4u + (lane >> 4);  // 16-slot group of the tile
+                const double v[6] = {lx, ly, lz, hx, hy, hz};
+#pragma unroll
+                for (int k = 0; k < 6; ++k) a.tile_box[(size_t)(30 + 16 * k + grp) * st + g] = v[k];
+            }
+#pragma unroll
+            for (int m = 16; m <= 32; m <<= 1) {
+                lx = fmin(lx, __shfl_xor(lx, m));
+                ly = fmin(ly, __shfl_xor(ly, m));
+                lz = fmin(lz, __shfl_xor(lz, m));
+                hx = fmax(hx, __shfl_xor(hx, m));
+                hy = fmax(hy, __shfl_xor(hy, m));
+                hz = fmax(hz, __shfl_xor(hz, m));
+            }
+            if (lane == 0) {
+                const double v[6] = {lx, ly, lz, hx, hy, hz};
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    a.tile_box[(size_t)(6 + 4 * k + wave) * st + g] = v[k];
+                    qbox[g][wave][k] = v[k];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t q = threadIdx.x; q < 6u * a.n_tiles; q += kStepThreads) {
+        const uint32_t g = q / 6u, k = q % 6u;
+        double v = qbox[g][0][k];
+        for (int w = 1; w < 4; ++w) v = (k < 3) ? fmin(v, qbox[g][w][k]) : fmax(v, qbox[g][w][k]);
+        a.tile_box[(size_t)k * st + g] = v;
+    }
+}
+
+template <bool FUSE>
 __global__ __launch_bounds__(kStepThreads) void step_update(StepArgs a) {
     const uint32_t step = a.step + (a.step_base ? *a.step_base : 0u);
     // travelling holes at the start of this step, of the next one, and the
@@ -1861,10 +1992,33 @@ __global__ __launch_bounds__(kStepThreads) void step_update(StepArgs a) {
         if (t) atomicAdd(cnt_out, t);
         if (pr && a.coulomb) atomicAdd(&a.stats[1], pr);
     }
+    if constexpr (FUSE) {
+        // the last workgroup to arrive rebuilds the list: each thread's
+        // stores of the step are made visible at device scope before its
+        // workgroup arrives, and the last one sees every workgroup's
+        __shared__ uint32_t last;
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) last = atomicAdd(a.arrive, 1u) == gridDim.x - 1u ? 1u : 0u;
+        __syncthreads();
+        if (last) {
+            __threadfence();
+            if (threadIdx.x == 0) atomicExch(a.arrive, 0u);  // zero for the next launch
+            build_small_list(a);
+        }
+    }
 }
 
 hipError_t launch_step(const StepArgs& a, uint32_t n_slots, hipStream_t s) {
-    step_update<<<grid_for(n_slots, kStepThreads, 16384), kStepThreads, 0, s>>>(a);
+    if (a.arrive) {
+        // the rebuilt list needs every slot and tile in one workgroup's LDS
+        if (!a.list_mode || n_slots != a.n_all || n_slots > (uint32_t)kFusedList ||
+            a.n_tiles > (uint32_t)kFusedTiles)
+            return hipErrorInvalidValue;
+        step_update<true><<<grid_for(n_slots, kStepThreads, 16384), kStepThreads, 0, s>>>(a);
+    } else {
+        step_update<false><<<grid_for(n_slots, kStepThreads, 16384), kStepThreads, 0, s>>>(a);
+    }
     return hipGetLastError();
 }
 

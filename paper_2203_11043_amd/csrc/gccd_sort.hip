@@ -14,45 +14,15 @@
 // five levels.  The kernels only read and write the two key buffers (no
 // memory-set commands, no temporary storage, no host synchronisation), so a
 // sequence of steps that sorts can be captured in a HIP graph.
-#include "gccd_internal.h"
+#include "gccd_sort_dev.h"
 
 namespace gccd {
 
 constexpr int kSortThreads = 512;
-constexpr int kSortItems = 8;
 constexpr uint32_t kSortTile = kSortThreads * kSortItems;  // 4096
 
-__device__ __forceinline__ void compare_exchange(uint64_t& a, uint64_t& b, bool up) {
-    if ((a > b) == up) {
-        const uint64_t t = a;
-        a = b;
-        b = t;
-    }
-}
-
-// LDS slot of position i of a tile: one pad word after every kSortItems
-// keys, so that the kSortItems consecutive keys of each lane (a stride of
-// kSortItems + 1 words between lanes) spread over the banks.
-__device__ __forceinline__ uint32_t lds_slot(uint32_t i) { return i + i / kSortItems; }
-
-// Ascending sort of a lane's kSortItems keys in registers (bitonic network).
-__device__ __forceinline__ void register_sort(uint64_t (&v)[kSortItems]) {
-#pragma unroll
-    for (uint32_t k = 2; k <= (uint32_t)kSortItems; k <<= 1)
-#pragma unroll
-        for (uint32_t j = k >> 1; j > 0; j >>= 1)
-#pragma unroll
-            for (uint32_t e = 0; e < (uint32_t)kSortItems; ++e)
-                if ((e & j) == 0u) compare_exchange(v[e], v[e | j], (e & k) == 0u);
-}
-
-// One tile of T = THREADS * kSortItems keys: each lane sorts kSortItems
-// consecutive keys in registers, then log2(T / kSortItems) levels merge
-// pairs of sorted runs in LDS, each lane writing kSortItems consecutive
-// outputs of its pair (found by a binary search on the merge path, then a
-// sequential merge).  Every level moves each key once through LDS (a bitonic
-// network moves it once per stage, log2 of the run length stages per
-// level).  Loads and stores of global memory are coalesced through LDS.
+// One tile of T = THREADS * kSortItems keys per workgroup, sorted in LDS
+// (block_sort_lds); loads and stores of global memory are coalesced.
 template <int THREADS>
 __global__ __launch_bounds__(THREADS) void block_sort(const uint64_t* in, uint64_t* out,
                                                       uint32_t n) {
@@ -60,52 +30,7 @@ __global__ __launch_bounds__(THREADS) void block_sort(const uint64_t* in, uint64
     __shared__ uint64_t s[T + T / kSortItems];
     const uint32_t b0 = blockIdx.x * T;
     const uint32_t cnt = min(T, n - b0);
-    const uint32_t first = threadIdx.x * kSortItems;
-    // padding sorts last (a key equal to the padding value is the same value)
-    for (uint32_t i = threadIdx.x; i < T; i += THREADS)
-        s[lds_slot(i)] = i < cnt ? in[b0 + i] : ~0ull;
-    __syncthreads();
-    uint64_t v[kSortItems];
-#pragma unroll
-    for (uint32_t e = 0; e < (uint32_t)kSortItems; ++e) v[e] = s[lds_slot(first + e)];
-    register_sort(v);
-    for (uint32_t w = kSortItems; w < T; w <<= 1) {
-        __syncthreads();  // every read of s is done before it is written again
-#pragma unroll
-        for (uint32_t e = 0; e < (uint32_t)kSortItems; ++e) s[lds_slot(first + e)] = v[e];
-        __syncthreads();
-        // outputs [k, k + kSortItems) of the merge of runs A = [base, base + w)
-        // and B = [base + w, base + 2 w) (both full: T is a power of two)
-        const uint32_t base = first / (2 * w) * (2 * w);
-        const uint32_t k = first - base, A = base, B = base + w;
-        uint32_t lo = k > w ? k - w : 0u, hi = min(k, w);
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (s[lds_slot(A + mid)] > s[lds_slot(B + k - 1u - mid)])
-                hi = mid;
-            else
-                lo = mid + 1u;
-        }
-        uint32_t ia = lo, ib = k - lo;
-        uint64_t a = ia < w ? s[lds_slot(A + ia)] : ~0ull;
-        uint64_t b = ib < w ? s[lds_slot(B + ib)] : ~0ull;
-#pragma unroll
-        for (uint32_t e = 0; e < (uint32_t)kSortItems; ++e) {
-            if (ib >= w || (ia < w && a < b)) {
-                v[e] = a;
-                ++ia;
-                a = ia < w ? s[lds_slot(A + ia)] : ~0ull;
-            } else {
-                v[e] = b;
-                ++ib;
-                b = ib < w ? s[lds_slot(B + ib)] : ~0ull;
-            }
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (uint32_t e = 0; e < (uint32_t)kSortItems; ++e) s[lds_slot(first + e)] = v[e];
-    __syncthreads();
+    block_sort_lds<THREADS>(in + b0, cnt, s);
     for (uint32_t i = threadIdx.x; i < cnt; i += THREADS) out[b0 + i] = s[lds_slot(i)];
 }
 
