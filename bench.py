@@ -288,8 +288,11 @@ def main() -> int:
                     help="one gccd_run call and one image per time step (a host round trip "
                          "per step) instead of one call for all timed steps")
     ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the automatic launch shape instead of measuring the "
-                         "candidates first (gccd_autotune)")
+                    help="batch workload: keep the automatic launch shape instead of "
+                         "measuring the candidates first (gccd_autotune)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="single cloud: measure the candidate launch shapes first "
+                         "(gccd_autotune) instead of the automatic shape")
     ap.add_argument("--no-closure", action="store_true",
                     help="skip the closure-versus-exact leg on the 1e6-hole cloud")
     ap.add_argument("--schedule", choices=("grid", "queue", "graph"), default="grid",
@@ -383,7 +386,11 @@ def main() -> int:
 
         def image():
             gccd.gccd_image(ctx, 0.0, 0.0, w.pitch_um, w.nx, w.ny, counts, nout)
-    if not args.no_autotune and not (args.tpt or args.chunks):
+    # the batch is autotuned by default; the single cloud keeps the automatic
+    # shape (the counters of the committed traffic record were taken in it,
+    # and the tuner finds nothing faster there)
+    want_tune = args.autotune if args.workload == "cloud" else not args.no_autotune
+    if want_tune and not (args.tpt or args.chunks):
         tuned = gccd.gccd_autotune(ctx)
 
     def run(k):

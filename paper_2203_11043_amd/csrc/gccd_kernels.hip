@@ -8,6 +8,7 @@
 // Several independent events (clouds) can share one launch; every kernel
 // keeps them apart through the per-event slot offsets.
 #include "gccd.h"
+#include "gccd_fp64.h"
 #include "gccd_internal.h"
 #include "gccd_sort_dev.h"
 
@@ -1668,14 +1669,14 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32
     constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t hiA = __umulhi(kMulA, c0), loA = kMulA * c0;
-        const uint32_t hiB = __umulhi(kMulB, c2), loB = kMulB * c2;
-        const uint32_t n0 = hiB ^ c1 ^ k0;
-        const uint32_t n2 = hiA ^ c3 ^ k1;
+        // one 32 x 32 -> 64-bit multiply-add instruction gives both halves
+        const uint64_t pA = (uint64_t)kMulA * c0, pB = (uint64_t)kMulB * c2;
+        const uint32_t n0 = (uint32_t)(pB >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(pA >> 32) ^ c3 ^ k1;
         c0 = n0;
-        c1 = loB;
+        c1 = (uint32_t)pB;
         c2 = n2;
-        c3 = loA;
+        c3 = (uint32_t)pA;
         k0 += kWeylA;
         k1 += kWeylB;
     }
@@ -1811,8 +1812,34 @@ __device__ __forceinline__ void build_small_list(const StepArgs& a) {
     }
 }
 
-template <bool FUSE>
-__global__ __launch_bounds__(kStepThreads) void step_update(StepArgs a) {
+// The FP64 functions of the step (gccd_fp64.h).  Carrier mode (no
+// repulsion) is bound by VALU issue and takes the three-operand Horner steps
+// (4.7e10 against 4.2e10 carrier-steps/s at 2^24 holes); list mode, which
+// streams the partial sums, the compiler's own (114 against 139 VGPRs).
+// Against the device library's versions: 26.7 against 27.1 us per list step
+// at 1e5 holes, 1.97 against 2.08 ms at the 4096-cloud batch.
+template <bool LIST>
+__device__ __forceinline__ double exp_s(double x) {
+    return fp64::exp<!LIST>(x);
+}
+template <bool LIST>
+__device__ __forceinline__ double log_s(double x) {
+    return fp64::log<!LIST>(x);
+}
+template <bool LIST>
+__device__ __forceinline__ double log1p_s(double x) {
+    return fp64::log1p<!LIST>(x);
+}
+template <bool LIST>
+__device__ __forceinline__ void sincospi_s(double x, double* s, double* c) {
+    fp64::sincospi<!LIST>(x, s, c);
+}
+
+// LIST: list mode (a.list_mode, Coulomb on); carrier mode is a kernel of
+// its own (drift_update), without the list code, for the step without
+// repulsion.
+template <bool FUSE, bool LIST>
+__device__ __forceinline__ void step_body(const StepArgs& a) {
     const uint32_t step = a.step + (a.step_base ? *a.step_base : 0u);
     // travelling holes at the start of this step, of the next one, and the
     // counter of the step after next (cleared now; nobody reads it)
@@ -1837,7 +1864,7 @@ __global__ __launch_bounds__(kStepThreads) void step_update(StepArgs a) {
             uint32_t e, j, local, src = 0u;
             bool active;
             uint64_t key = 0;
-            if (a.list_mode) {
+            if (LIST) {
                 // the list may be one step old (its travelling segment then
                 // still holds the holes collected in the last step): the
                 // carrier's own collection step decides
@@ -1866,7 +1893,7 @@ __global__ __launch_bounds__(kStepThreads) void step_update(StepArgs a) {
             if (active) {
                 pairs += src;  // sources of the Eq. (6) sum at this target
                 double ecx = 0.0, ecy = 0.0, ecz = 0.0;
-                if (a.coulomb) {
+                if (LIST && a.coulomb) {
                     double sx = 0.0, sy = 0.0, sz = 0.0;
                     const int nchunk = a.ev_chunks[e];
                     const float* pp = a.part + slot;
@@ -1932,8 +1959,9 @@ __global__ __launch_bounds__(kStepThreads) void step_update(StepArgs a) {
                     // mu0 exp(-log1p(y) / beta) with y = exp(beta (log|E|^2 / 2
                     // - log Ec)): four transcendentals instead of two general
                     // powers and a square root (|E| = 0 gives y = 0, mu = mu0)
-                    const double y = exp(a.beta * (0.5 * log(ex * ex + ey * ey + ez * ez) - a.log_ec));
-                    mu = a.mu0 * exp(-a.inv_beta * log1p(y));
+                    const double y =
+                        exp_s<LIST>(a.beta * (0.5 * log_s<LIST>(ex * ex + ey * ey + ez * ez) - a.log_ec));
+                    mu = a.mu0 * exp_s<LIST>(-a.inv_beta * log1p_s<LIST>(y));
                 }
                 // v = mu E in cm/s; v dt in cm; 1 cm = 1e4 um
                 double dx = mu * ex * a.dt_s * 1e4;
@@ -1942,13 +1970,14 @@ __global__ __launch_bounds__(kStepThreads) void step_update(StepArgs a) {
                 if (a.diffusion) {
                     uint32_t w0 = local, w1 = step, w2 = a.event0 + e, w3 = 0u;
                     philox4x32_10(w0, w1, w2, w3, a.key0, a.key1);
-                    const double r01 = sqrt(-2.0 * log(unit_open(w0)));
-                    const double r23 = sqrt(-2.0 * log(unit_open(w2)));
+                    const double r01 = sqrt(-2.0 * log_s<LIST>(unit_open(w0)));
+                    const double r23 = sqrt(-2.0 * log_s<LIST>(unit_open(w2)));
                     // the angles 2 pi u in half-turns: 2 u is exact, and one
-                    // argument reduction serves both sine and cosine of the first
-                    double s1, c1;
-                    sincospi(2.0 * unit_open(w1), &s1, &c1);
-                    const double c3 = cospi(2.0 * unit_open(w3));
+                    // argument reduction serves both sine and cosine
+                    double s1, c1, s3, c3;
+                    sincospi_s<LIST>(2.0 * unit_open(w1), &s1, &c1);
+                    sincospi_s<LIST>(2.0 * unit_open(w3), &s3, &c3);
+                    (void)s3;
                     const double D = a.vt * mu;                        // Eq. (4), cm^2/s
                     const double sigma = sqrt(2.0 * D * a.dt_s) * 1e4;  // Eq. (3), um
                     dx += sigma * (r01 * c1);
@@ -1965,9 +1994,9 @@ __global__ __launch_bounds__(kStepThreads) void step_update(StepArgs a) {
                 const bool collected = zn <= a.z_well;
                 if (collected) a.cstep[j] = (int32_t)(step + 1u);
                 keep = !collected;
-                if (a.list_mode) key = make_key(e, collected, xn, yn, zn, local, a.kl);
+                if (LIST) key = make_key(e, collected, xn, yn, zn, local, a.kl);
             }
-            if (a.list_mode) a.keys_out[slot] = key;
+            if (LIST) a.keys_out[slot] = key;
         }
         kept += (uint32_t)__popcll(__ballot(keep));
     }
@@ -2009,6 +2038,15 @@ __global__ __launch_bounds__(kStepThreads) void step_update(StepArgs a) {
     }
 }
 
+template <bool FUSE>
+__global__ __launch_bounds__(kStepThreads) void step_update(StepArgs a) {
+    step_body<FUSE, true>(a);
+}
+
+__global__ __launch_bounds__(kStepThreads) void drift_update(StepArgs a) {
+    step_body<false, false>(a);
+}
+
 hipError_t launch_step(const StepArgs& a, uint32_t n_slots, hipStream_t s) {
     if (a.arrive) {
         // the rebuilt list needs every slot and tile in one workgroup's LDS
@@ -2016,8 +2054,10 @@ hipError_t launch_step(const StepArgs& a, uint32_t n_slots, hipStream_t s) {
             a.n_tiles > (uint32_t)kFusedTiles)
             return hipErrorInvalidValue;
         step_update<true><<<grid_for(n_slots, kStepThreads, 16384), kStepThreads, 0, s>>>(a);
-    } else {
+    } else if (a.list_mode) {
         step_update<false><<<grid_for(n_slots, kStepThreads, 16384), kStepThreads, 0, s>>>(a);
+    } else {
+        drift_update<<<grid_for(n_slots, kStepThreads, 16384), kStepThreads, 0, s>>>(a);
     }
     return hipGetLastError();
 }

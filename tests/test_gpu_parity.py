@@ -245,18 +245,14 @@ def run_both(g, W, orc, w, steps, **kw):
 
 def test_step_full_size_every_hole(g, W, orc, step_bound):
     """One whole step on the 1e5-hole cloud, in the launch configuration of
-    the benchmark (the autotuned shape): every hole's new position agrees
-    with the oracle's FP64 step to the displacement that the field tolerance
-    (1e-5 A_j) allows, plus device-libm rounding; no hole is collected in
-    that step on either side."""
+    the benchmark: every hole's new position agrees with the oracle's FP64
+    step to the displacement that the field tolerance (1e-5 A_j) allows, plus
+    device-libm rounding; no hole is collected in that step on either side."""
     w = W.single_cloud(100000, seed=1)
     p, d = dev_params(g, W)
     ctx = g.gccd_init(p)
     try:
         g.gccd_load(ctx, *gpu_tensors(w.x, w.y, w.z))
-        tpt, chunks, _ = g.gccd_autotune(ctx)
-        print(f"[step] autotuned: tpt {tpt}, chunks {chunks}, "
-              f"tile {g.gccd_stats(ctx)['tile_sources']}", flush=True)
         done, na = g.gccd_run(ctx, w.dt_ps, 1)
         pos, cs = g.gccd_positions(ctx, w.n)
         pos, cs = pos.cpu().numpy(), cs.cpu().numpy()
