@@ -26,6 +26,13 @@ constexpr double kEps0 = 8.8541878128e-12;
 constexpr double kPi = 3.14159265358979323846;
 
 constexpr int kPoll = 32;                       // steps between host reads of the counts
+// Pair interactions per step from which the exact path pipelines its list
+// (sorts the next step's keys on a second stream while the field runs).
+// Below it the field launch is too short to hide the sort, and the sort's
+// workgroups, which fit beside the field kernel's on no compute unit, wait
+// for them and stretch the field launch's tail instead (measured on the muon
+// track: 0.69 against 0.42 ms per step over its run).
+constexpr double kPipeMinPairs = 5e9;
 constexpr int64_t kMaxCarriers = 2147483647LL;  // slots are 32-bit
 
 // Device block of counters (32-bit words): a ring of three travelling-hole
@@ -119,6 +126,8 @@ struct gccd_ctx {
     int tpt_fixed = 0, chunks_fixed = 0;
     int tpt = 1;
     int unit = kTile;       // sources per staged tile of the Eq. (6) launch (choose_unit)
+    int pipe_mode = -1;     // the list pipelined (1) or not (0); decided at load and
+                            // at every step that is a multiple of kPoll
     int unit_fixed = 0;     // gccd_set_tile: 0 automatic
     int precision = GCCD_PRECISION_DEFAULT;
 
@@ -140,7 +149,7 @@ struct gccd_ctx {
     int64_t closure_steps = 0;
 
     // how gccd_run issues the steps (GCCD_SCHEDULE_*), and the captured graph
-    int schedule = GCCD_SCHEDULE_GRID;
+    int schedule = GCCD_SCHEDULE_GRAPH;
     uint32_t* sched = nullptr;       // [kSchedWords]
     uint32_t* host_sched = nullptr;  // pinned [kSchedWords]
     int queue_slots = 0;             // workgroups of the persistent launch per CU (0: not yet asked)
@@ -151,6 +160,7 @@ struct gccd_ctx {
                                       // may be the null stream, which cannot capture)
     bool graph_refused = false;      // a capture for this load failed or held a memset node
     int graph_cur = -1, graph_u = -1;  // the list buffers the captured steps start from
+    int graph_pipe = -1;               // ... and whether they pipeline the list
     int64_t graph_replays = 0;
 
     bool timing = false;
@@ -588,9 +598,9 @@ FieldArgs field_args(const gccd_ctx* c, bool targets_all) {
     return fa;
 }
 
-// Workgroups of the persistent launch, or 0 for one workgroup per item.
+// Workgroups of the persistent launch (the queue schedule), or 0.
 uint32_t queue_grid(gccd_ctx* c) {
-    if (c->schedule == GCCD_SCHEDULE_GRID || c->tpt != 1 ||
+    if (c->schedule != GCCD_SCHEDULE_QUEUE || c->tpt != 1 ||
         c->precision != GCCD_PRECISION_DEFAULT)
         return 0;
     if (c->queue_slots == 0) c->queue_slots = field_queue_slots_per_cu();
@@ -598,6 +608,17 @@ uint32_t queue_grid(gccd_ctx* c) {
     // so a captured graph stays valid as the items shrink)
     const size_t slots = (size_t)c->n_cu * (size_t)c->queue_slots;
     return (uint32_t)std::max<size_t>(1, std::min(slots, c->items_cap));
+}
+
+// The graph schedule's launch: one workgroup per item of the load's item
+// capacity, those past the item count in device memory leaving at once
+// (fixed per load, so a captured graph stays valid as the items shrink);
+// 0 for the other schedules and shapes.
+uint32_t graph_cap(const gccd_ctx* c) {
+    if (c->schedule != GCCD_SCHEDULE_GRAPH || c->tpt != 1 ||
+        c->precision != GCCD_PRECISION_DEFAULT)
+        return 0;
+    return (uint32_t)std::max<size_t>(1, c->items_cap);
 }
 
 // The current positions in the slot order of keys[cur], and the boxes of
@@ -1079,6 +1100,7 @@ int gccd_load_events(gccd_ctx* c, int32_t n_events, const int64_t* offsets, cons
     c->list_mode = c->p.coulomb != 0;
     c->cur = 0;
     c->u = 0;
+    c->pipe_mode = -1;
     if (c->list_mode) {
         GCCD_HIP(c, launch_make_keys(c->x, c->y, c->z, c->cstep, c->ev_of, c->ev_off_d,
                                      (uint32_t)n, c->kl, c->ukeys[0], c->stream));
@@ -1294,7 +1316,8 @@ int gccd_autotune(gccd_ctx* c, int32_t* targets_per_thread, int32_t* source_chun
                 float t[3];
                 for (int rep = 0; rep < 4 && r == GCCD_OK; ++rep) {  // one untimed, three timed
                     if (hipEventRecord(e0, c->stream) != hipSuccess ||
-                        launch_field(fa, c->tpt, c->precision, c->n_items, queue_grid(c), c->stream) !=
+                        launch_field(fa, c->tpt, c->precision, c->n_items, queue_grid(c), c->stream,
+                                     graph_cap(c)) !=
                             hipSuccess ||
                         hipEventRecord(e1, c->stream) != hipSuccess ||
                         hipEventSynchronize(e1) != hipSuccess)
@@ -1417,12 +1440,29 @@ int gccd_run(gccd_ctx* c, double dt_ps, int64_t max_steps, int64_t* steps_done,
 
     // A small load's step kernel rebuilds the list itself (its last
     // workgroup sorts, counts and gathers: two launches per step).  Other
-    // exact steps with every hole a source are pipelined (see gccd_ctx::keys);
-    // the others need the list of the positions they run over.
+    // exact steps with every hole a source are pipelined (see gccd_ctx::keys)
+    // while their pair work hides the sort (kPipeMinPairs); the others need
+    // the list of the positions they run over.  The choice is made at load
+    // and at every step that is a multiple of kPoll (the polls are aligned to
+    // those steps), from the counts there, so a run gives the same bits however
+    // it is split into calls.
     const bool fused = c->list_mode && !use_closure && n <= (uint32_t)kFusedList &&
                        c->n_tiles <= (uint32_t)kFusedTiles;
-    const bool pipelined =
-        !fused && c->list_mode && !use_closure && c->p.collected_are_sources;
+    const bool pipe_ok = !fused && c->list_mode && !use_closure && c->p.collected_are_sources;
+    auto decide_pipe = [&]() -> int {
+        if (!pipe_ok) return 0;
+        double pairs = 0.0;
+        for (uint32_t e = 0; e < c->n_events; ++e) {
+            const double a = (double)c->host_active[e];
+            pairs += a * (c->p.collected_are_sources ? (double)(c->off_h[e + 1] - c->off_h[e]) : a);
+        }
+        return pairs >= kPipeMinPairs ? 1 : 0;
+    };
+    if (!pipe_ok)
+        c->pipe_mode = 0;
+    else if (c->pipe_mode < 0 || step0 % kPoll == 0)
+        c->pipe_mode = decide_pipe();
+    bool pipelined = c->pipe_mode == 1;
     if (fused) {
         sa.arrive = c->sched + kSchedArrive;
         sa.n_events = c->n_events;
@@ -1435,28 +1475,36 @@ int gccd_run(gccd_ctx* c, double dt_ps, int64_t max_steps, int64_t* steps_done,
         sa.tile_box = c->tile_box;
         sa.box_stride = std::max<uint32_t>(c->n_tiles, 1);
     }
-    if (c->list_mode && !pipelined) {
-        int r = settle(c);
+    // Puts the list state in line with `pipelined`.
+    auto enter_mode = [&]() -> int {
+        if (c->list_mode && !pipelined) {
+            int r = settle(c);
+            if (r != GCCD_OK) return r;
+        }
+        if (pipelined && !c->side) {
+            GCCD_HIP(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+            GCCD_HIP(c, hipEventCreateWithFlags(&c->ev_keys, hipEventDisableTiming));
+            GCCD_HIP(c, hipEventCreateWithFlags(&c->ev_list, hipEventDisableTiming));
+        }
+        if (pipelined && !c->sorting && bound > 0) {
+            // Enter the steady state: the next step's list (the current one) also
+            // stands in keys[cur ^ 1] as if the side stream had sorted it.  The
+            // next two steps run over the same list either way, so results do not
+            // change; every stretch then starts alike and can be captured.
+            const size_t kb = (size_t)c->n * sizeof(uint64_t);
+            GCCD_HIP(c, hipMemcpyAsync(c->keys[c->cur ^ 1], c->keys[c->cur], kb,
+                                       hipMemcpyDeviceToDevice, c->stream));
+            GCCD_HIP(c, hipMemcpyAsync(c->ev_active_d[c->cur ^ 1], c->ev_active_d[c->cur],
+                                       c->n_events * sizeof(uint32_t), hipMemcpyDeviceToDevice,
+                                       c->stream));
+            GCCD_HIP(c, hipEventRecord(c->ev_list, c->stream));
+            c->sorting = true;
+        }
+        return GCCD_OK;
+    };
+    {
+        int r = enter_mode();
         if (r != GCCD_OK) return r;
-    }
-    if (pipelined && !c->side) {
-        GCCD_HIP(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
-        GCCD_HIP(c, hipEventCreateWithFlags(&c->ev_keys, hipEventDisableTiming));
-        GCCD_HIP(c, hipEventCreateWithFlags(&c->ev_list, hipEventDisableTiming));
-    }
-    if (pipelined && !c->sorting && bound > 0) {
-        // Enter the steady state: the next step's list (the current one) also
-        // stands in keys[cur ^ 1] as if the side stream had sorted it.  The
-        // next two steps run over the same list either way, so results do not
-        // change; every stretch then starts alike and can be captured.
-        const size_t kb = (size_t)c->n * sizeof(uint64_t);
-        GCCD_HIP(c, hipMemcpyAsync(c->keys[c->cur ^ 1], c->keys[c->cur], kb,
-                                   hipMemcpyDeviceToDevice, c->stream));
-        GCCD_HIP(c, hipMemcpyAsync(c->ev_active_d[c->cur ^ 1], c->ev_active_d[c->cur],
-                                   c->n_events * sizeof(uint32_t), hipMemcpyDeviceToDevice,
-                                   c->stream));
-        GCCD_HIP(c, hipEventRecord(c->ev_list, c->stream));
-        c->sorting = true;
     }
     int64_t stretch = 0;  // steps of the stretch being issued
 
@@ -1479,7 +1527,7 @@ int gccd_run(gccd_ctx* c, double dt_ps, int64_t max_steps, int64_t* steps_done,
             } else {
                 FieldArgs fa = field_args(c, false);
                 GCCD_HIP(c, launch_field(fa, c->tpt, c->precision, c->n_items, queue_grid(c),
-                                         c->stream));
+                                         c->stream, graph_cap(c)));
             }
             if (evp) GCCD_HIP(c, hipEventRecord(evp[1], c->stream));
             sa.keys_in = c->keys[c->cur];
@@ -1519,11 +1567,14 @@ int gccd_run(gccd_ctx* c, double dt_ps, int64_t max_steps, int64_t* steps_done,
     // per-launch timing events cannot be read back from graph replays here:
     // with timing on, the steps are issued one by one
     const bool graphable = c->list_mode && !use_closure && !c->timing &&
-                           c->schedule == GCCD_SCHEDULE_GRAPH && queue_grid(c) > 0;
+                           graph_cap(c) > 0;
 
     int64_t k = 0;
     while (k < max_steps && bound > 0) {
-        const int64_t chunk_steps = (max_steps - k < kPoll) ? (max_steps - k) : kPoll;
+        // stretches end at multiples of kPoll (a call that starts between
+        // them first runs up to the next)
+        const int64_t to_poll = kPoll - (step0 + k) % kPoll;
+        const int64_t chunk_steps = (max_steps - k < to_poll) ? (max_steps - k) : to_poll;
         if (c->list_mode) {
             // the host copy is free: the stream was synchronised at the last poll
             c->host_sched[kSchedStep] = (uint32_t)(step0 + k);
@@ -1535,12 +1586,15 @@ int gccd_run(gccd_ctx* c, double dt_ps, int64_t max_steps, int64_t* steps_done,
         // a pipelined stretch is replayed from the list buffers it was
         // captured from (an even stretch leaves them as it found them)
         if (graphable && chunk_steps == kPoll && !c->graph_refused) {
-            if (c->graph_exec && (c->graph_cur != c->cur || c->graph_u != c->u)) drop_graph(c);
+            if (c->graph_exec && (c->graph_cur != c->cur || c->graph_u != c->u ||
+                                  c->graph_pipe != (pipelined ? 1 : 0)))
+                drop_graph(c);
             if (!c->graph_exec) {
                 int r = capture_steps(c, issue);
                 if (r != GCCD_OK) return r;
                 c->graph_cur = c->cur;
                 c->graph_u = c->u;
+                c->graph_pipe = pipelined ? 1 : 0;
             }
             if (c->graph_exec) {
                 GCCD_HIP(c, hipGraphLaunch(c->graph_exec, c->stream));
@@ -1568,6 +1622,15 @@ int gccd_run(gccd_ctx* c, double dt_ps, int64_t max_steps, int64_t* steps_done,
             c->loaded = false;
             return fail(c, GCCD_E_NONFINITE,
                         "gccd_run: a carrier position became non-finite; reload to continue");
+        }
+        if (pipe_ok && (step0 + k) % kPoll == 0) {
+            // the list pipelined or not for the next stretch
+            c->pipe_mode = decide_pipe();
+            if ((c->pipe_mode == 1) != pipelined && bound > 0 && k < max_steps) {
+                pipelined = c->pipe_mode == 1;
+                r = enter_mode();
+                if (r != GCCD_OK) return r;
+            }
         }
         if (c->list_mode && bound > 0 && k < max_steps) {
             r = rebuild();  // counts only shrink: fewer items
@@ -1619,7 +1682,8 @@ int gccd_field(gccd_ctx* c, double* ex, double* ey, double* ez) {
         r = build_items(c, all.data());
         if (r != GCCD_OK) return r;
         FieldArgs fa = field_args(c, true);
-        GCCD_HIP(c, launch_field(fa, c->tpt, c->precision, c->n_items, queue_grid(c), c->stream));
+        GCCD_HIP(c, launch_field(fa, c->tpt, c->precision, c->n_items, queue_grid(c), c->stream,
+                                 graph_cap(c)));
     }
     GCCD_HIP(c, launch_field_finish(
                     c->part, n, c->ev_chunks_d, 0, 0, c->keys[c->cur], c->ev_off_d, c->kl, n, c->K,

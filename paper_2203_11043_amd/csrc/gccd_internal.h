@@ -71,6 +71,8 @@ struct FieldArgs {
     uint32_t* queue;            // persistent launch: [0] next item (zero before the launch)
     int32_t near_compensated;   // one target per thread, default precision: tiles within
                                 // rho/4 take the compensated difference (small launches)
+    int32_t count_items;        // 1: the launch is sized to the item capacity and a
+                                // workgroup past *n_items leaves at once (graph schedule)
     int32_t unit;               // sources per staged tile of the one-target-per-thread
                                 // default kernel: kTile, kTile / 2 or kTile / 4 (the
                                 // items count tiles of that size; other kernels: kTile)
@@ -156,9 +158,11 @@ int field_slots_per_cu(int tpt, int precision);
 int field_queue_slots_per_cu();
 // queue_grid > 0: the persistent launch of that many workgroups (one target
 // per thread, default precision), after clearing the counter a.queue[0]
+// grid_cap > 0 (one target per thread, default precision): grid_cap
+// workgroups, those past the device-side item count *a.n_items leaving at
+// once, so that one captured launch serves every item count up to the cap.
 hipError_t launch_field(const FieldArgs& a, int tpt, int precision, uint32_t n_items,
-                        uint32_t queue_grid,
-                        hipStream_t s);
+                        uint32_t queue_grid, hipStream_t s, uint32_t grid_cap = 0);
 hipError_t launch_step(const StepArgs& a, uint32_t n_slots, hipStream_t s);
 hipError_t launch_load(double* z, int32_t* cstep, const uint32_t* ev_off, uint32_t* ev_of,
                        uint32_t n_events, uint32_t n, double thickness, double z_well,

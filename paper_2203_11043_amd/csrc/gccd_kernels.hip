@@ -984,6 +984,7 @@ __device__ __forceinline__ void expanded_item(const FieldArgs& a, const FieldIte
 // One workgroup per work item.
 template <bool COMP, int UNIT>
 __global__ __launch_bounds__(kFieldThreads) void field_tiles_expanded(FieldArgs a) {
+    if (a.count_items && blockIdx.x >= *a.n_items) return;  // the whole workgroup
     __shared__ __align__(16) ExpandedLds L;
     if (threadIdx.x == 0) L.xl.n = 0;  // ordered before any push by the item's first barrier
     expanded_item<COMP, UNIT>(a, a.items[blockIdx.x], L);
@@ -1419,7 +1420,30 @@ int field_slots_per_cu(int tpt, int precision) {
 }
 
 hipError_t launch_field(const FieldArgs& a, int tpt, int precision, uint32_t n_items,
-                        uint32_t queue_grid, hipStream_t s) {
+                        uint32_t queue_grid, hipStream_t s, uint32_t grid_cap) {
+    if (grid_cap > 0) {
+        if (tpt != 1 || precision != GCCD_PRECISION_DEFAULT || n_items > grid_cap)
+            return hipErrorInvalidValue;
+        FieldArgs b = a;
+        b.count_items = 1;
+        const bool c = b.near_compensated != 0;
+        switch (b.unit) {
+            case kTile / 4:
+                if (c) field_tiles_expanded<true, kTile / 4><<<grid_cap, kFieldThreads, 0, s>>>(b);
+                else field_tiles_expanded<false, kTile / 4><<<grid_cap, kFieldThreads, 0, s>>>(b);
+                break;
+            case kTile / 2:
+                if (c) field_tiles_expanded<true, kTile / 2><<<grid_cap, kFieldThreads, 0, s>>>(b);
+                else field_tiles_expanded<false, kTile / 2><<<grid_cap, kFieldThreads, 0, s>>>(b);
+                break;
+            case kTile:
+                if (c) field_tiles_expanded<true, kTile><<<grid_cap, kFieldThreads, 0, s>>>(b);
+                else field_tiles_expanded<false, kTile><<<grid_cap, kFieldThreads, 0, s>>>(b);
+                break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     if (queue_grid > 0 && tpt == 1 && precision == GCCD_PRECISION_DEFAULT) {
         // the item count is read on the device: launched even with none
         const hipError_t e = launch_fill_u32(a.queue, 1u, 0u, s);
@@ -1706,6 +1730,10 @@ __device__ __forceinline__ double unit_open(uint32_t w) {
 // and boxes as sort_keys, count_active and gather_tiles.  Wave w gathers
 // quarter w of every tile, four tiles at a time with all their loads in
 // flight together; the tile boxes are reduced from the quarters' in LDS.
+__device__ __forceinline__ double xor_f64(double v, uint32_t m) {
+    return __builtin_bit_cast(double, lane_xor(__builtin_bit_cast(uint64_t, v), m));
+}
+
 __device__ __forceinline__ void build_small_list(const StepArgs& a) {
     __shared__ uint64_t s[kFusedList + kFusedList / kSortItems];
     __shared__ uint32_t act[kFusedList];
@@ -1771,12 +1799,12 @@ __device__ __forceinline__ void build_small_list(const StepArgs& a) {
             }
 #pragma unroll
             for (int m = 1; m <= 8; m <<= 1) {
-                lx = fmin(lx, __shfl_xor(lx, m));
-                ly = fmin(ly, __shfl_xor(ly, m));
-                lz = fmin(lz, __shfl_xor(lz, m));
-                hx = fmax(hx, __shfl_xor(hx, m));
-                hy = fmax(hy, __shfl_xor(hy, m));
-                hz = fmax(hz, __shfl_xor(hz, m));
+                lx = fmin(lx, xor_f64(lx, m));
+                ly = fmin(ly, xor_f64(ly, m));
+                lz = fmin(lz, xor_f64(lz, m));
+                hx = fmax(hx, xor_f64(hx, m));
+                hy = fmax(hy, xor_f64(hy, m));
+                hz = fmax(hz, xor_f64(hz, m));
             }
             if ((lane & 15u) == 0) {
                 const uint32_t grp = wave * 4u + (lane >> 4);  // 16-slot group of the tile
@@ -1786,12 +1814,12 @@ __device__ __forceinline__ void build_small_list(const StepArgs& a) {
             }
 #pragma unroll
             for (int m = 16; m <= 32; m <<= 1) {
-                lx = fmin(lx, __shfl_xor(lx, m));
-                ly = fmin(ly, __shfl_xor(ly, m));
-                lz = fmin(lz, __shfl_xor(lz, m));
-                hx = fmax(hx, __shfl_xor(hx, m));
-                hy = fmax(hy, __shfl_xor(hy, m));
-                hz = fmax(hz, __shfl_xor(hz, m));
+                lx = fmin(lx, xor_f64(lx, m));
+                ly = fmin(ly, xor_f64(ly, m));
+                lz = fmin(lz, xor_f64(lz, m));
+                hx = fmax(hx, xor_f64(hx, m));
+                hy = fmax(hy, xor_f64(hy, m));
+                hz = fmax(hz, xor_f64(hz, m));
             }
             if (lane == 0) {
                 const double v[6] = {lx, ly, lz, hx, hy, hz};

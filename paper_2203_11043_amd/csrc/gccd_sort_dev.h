@@ -100,6 +100,15 @@ __device__ __forceinline__ void block_sort_lds(const uint64_t* in, uint32_t cnt,
     __syncthreads();
 }
 
+// 64-bit value of lane (this lane ^ m) of the wave: two LDS-crossbar
+// permutes with the byte index computed once.
+__device__ __forceinline__ uint64_t lane_xor(uint64_t v, uint32_t m) {
+    const int idx = (int)((__lane_id() ^ m) << 2);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(idx, (int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(idx, (int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // Compare-exchange stage of a bitonic network at distance J < K inside each
 // lane's K keys (element i = lane_base + r ascends where (i & k) == 0).
 template <int K, int J>
@@ -142,7 +151,7 @@ __device__ __forceinline__ void bitonic_sort_lanes(const uint64_t* in, uint32_t 
             if (m < 64u) {
 #pragma unroll
                 for (uint32_t r = 0; r < (uint32_t)K; ++r) {
-                    const uint64_t o = __shfl_xor(v[r], (int)m);
+                    const uint64_t o = lane_xor(v[r], m);
                     v[r] = ((o < v[r]) == keep_min) ? o : v[r];
                 }
             } else {
@@ -164,5 +173,6 @@ __device__ __forceinline__ void bitonic_sort_lanes(const uint64_t* in, uint32_t 
     for (uint32_t r = 0; r < (uint32_t)K; ++r) s[lds_slot(base + r)] = v[r];
     __syncthreads();
 }
+
 
 }  // namespace gccd

@@ -132,7 +132,7 @@ def test_schedule_validation(g, W):
     try:
         assert g.lib.gccd_set_schedule(ctx, 3) == g.GCCD_E_INVALID
         assert g.lib.gccd_set_schedule(ctx, -1) == g.GCCD_E_INVALID
-        assert g.gccd_stats(ctx)["schedule"] == 0          # the default: grid
+        assert g.gccd_stats(ctx)["schedule"] == 2          # the default: graph
     finally:
         g.gccd_destroy(ctx)
 
