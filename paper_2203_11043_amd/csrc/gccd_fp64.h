@@ -1,18 +1,20 @@
 // FP64 elementary functions of the time step (Eq. (2) mobility and the
-// Box-Muller transform of the diffusion step, Eqs. (3)-(4)), written from
-// their series: exp from its Taylor series after reduction by powers of two,
-// log from the series of 2 atanh((m - 1)/(m + 1)), log1p from log(1 + y)
-// corrected for the rounding of 1 + y, and sin/cos of pi r from their Taylor
-// series after reduction by half turns.  Each is accurate to 2 units in the
-// last place over the arguments the step gives them and their whole ranges
+// Box-Muller transform of the diffusion step, Eqs. (3)-(4)): exp after
+// reduction by powers of two, log from 2 atanh((m - 1)/(m + 1)), log1p from
+// log(1 + y) corrected for the rounding of 1 + y, sin/cos of pi r after
+// reduction by half turns, each with a near-minimax polynomial on the
+// reduced interval (coefficients printed by fp64_coefficients.py from
+// 40-digit Chebyshev fits), and the reciprocal and square root by Newton
+// steps from a hardware estimate.  Each is accurate to 2 units in the last
+// place over the arguments the step gives them and their whole ranges
 // (checked against 40-digit references on the host); the general-purpose
-// library versions spend about
-// twice the instructions on guarantees the step does not need (correct
-// rounding of every argument, extended internal precision), and the step
-// without repulsion is bound by instruction issue.
+// library versions spend about twice the instructions on guarantees the step
+// does not need (correct rounding of every argument, scaling for subnormal
+// inputs), and the step without repulsion is bound by instruction issue.
 //
-// Only fma, frexp, ldexp, rint and IEEE division and comparison are used,
-// so the same code compiles for the host, where the tests measure its error.
+// Only fma, frexp, ldexp, rint, IEEE comparison and the two estimates are
+// used; the host build takes its estimates from single precision and then
+// the same Newton steps, so the tests measure the same algorithm.
 #pragma once
 
 #include <math.h>
@@ -46,6 +48,35 @@ GCCD_HD inline double horner(double p, double r, double c) {
     return fma(p, r, c);
 }
 
+// 1/x for finite x > 0 with a normal reciprocal: two Newton steps
+// y <- y + y (1 - x y) from an estimate good to about 2^-22 (the hardware's
+// on the device, single precision on the host), each squaring the error.
+GCCD_HD inline double recip(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    double y = __builtin_amdgcn_rcp(x);
+#else
+    double y = (double)(1.0f / (float)x);
+#endif
+    y = fma(y, fma(-x, y, 1.0), y);
+    return fma(y, fma(-x, y, 1.0), y);
+}
+
+// sqrt(x) for finite normal x > 0: from an estimate y of 1/sqrt(x), one
+// coupled Newton step on g = x y (towards sqrt x) and h = y / 2, then a
+// final correction of g by its residual x - g^2.
+GCCD_HD inline double sqrt_pos(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const double y = __builtin_amdgcn_rsq(x);
+#else
+    const double y = (double)(1.0f / sqrtf((float)x));
+#endif
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    return fma(h, fma(-g, g, x), g);
+}
+
 // ln 2 split for exact products k * kLn2Hi with |k| < 2^11 (kLn2Hi has 42
 // significant bits); kLn2Lo = ln 2 - kLn2Hi rounded.
 constexpr double kLn2Hi = 0x1.62e42fefa3800p-1;
@@ -54,8 +85,8 @@ constexpr double kLog2E = 1.4426950408889634;  // 1 / ln 2
 constexpr double kSqrtHalf = 0.7071067811865476;
 
 // e^x.  x = k ln 2 + r, |r| <= ln 2 / 2 (Cody-Waite reduction with the
-// split ln 2; the first product is exact), e^r by its Taylor series to r^13
-// (the first omitted term is below 5e-18 of the sum), times 2^k.
+// split ln 2; the first product is exact), e^r by a degree-11 polynomial
+// (relative error 1.7e-17 on the interval), times 2^k.
 template <bool F3 = false>
 GCCD_HD inline double exp(double x) {
     if (x != x) return x;
@@ -63,29 +94,27 @@ GCCD_HD inline double exp(double x) {
     if (x < -745.2) return 0.0;
     const double k = rint(x * kLog2E);
     const double r = fma(-k, kLn2Lo, fma(-k, kLn2Hi, x));
-    double p = 1.6059043836821613e-10;  // 1/13!
-    p = horner<F3>(p, r, 2.08767569878681e-09);
-    p = horner<F3>(p, r, 2.505210838544172e-08);
-    p = horner<F3>(p, r, 2.755731922398589e-07);
-    p = horner<F3>(p, r, 2.7557319223985893e-06);
-    p = horner<F3>(p, r, 2.48015873015873e-05);
-    p = horner<F3>(p, r, 0.0001984126984126984);
-    p = horner<F3>(p, r, 0.001388888888888889);
-    p = horner<F3>(p, r, 0.008333333333333333);
-    p = horner<F3>(p, r, 0.041666666666666664);
-    p = horner<F3>(p, r, 0.16666666666666666);
-    p = horner<F3>(p, r, 0.5);
+    double p = 2.5110037721946562e-08;
+    p = horner<F3>(p, r, 2.7632639789868395e-07);
+    p = horner<F3>(p, r, 2.7557240918265525e-06);
+    p = horner<F3>(p, r, 2.480148548192088e-05);
+    p = horner<F3>(p, r, 0.00019841269890047406);
+    p = horner<F3>(p, r, 0.0013888888952315155);
+    p = horner<F3>(p, r, 0.008333333333319601);
+    p = horner<F3>(p, r, 0.04166666666648809);
+    p = horner<F3>(p, r, 0.1666666666666668);
+    p = horner<F3>(p, r, 0.5000000000000019);
     p = horner<F3>(p, r, 1.0);
     p = horner<F3>(p, r, 1.0);
     return ldexp(p, (int)k);
 }
 
 // ln x.  x = 2^e m with m in [sqrt(1/2), sqrt(2)); ln m = 2 atanh(f),
-// f = (m - 1)/(m + 1), |f| <= 0.1716, by its series to f^23 (the first
-// omitted term is below 1e-18 of the sum); ln x = e ln 2 + ln m.  f is
-// carried as f + f_lo (the residual of the division, with m + 1 split
-// exactly into its rounded value and error), so that 2 f, the leading term,
-// is nearly exact.
+// f = (m - 1)/(m + 1), |f| <= 0.1716, taken as 2 f + f s q(s), s = f^2, with
+// q a degree-6 polynomial (relative error 4.7e-16 in a term below 1 % of
+// the sum); ln x = e ln 2 + ln m.  f is carried as f + f_lo (the residual
+// of the division, with m + 1 split exactly into its rounded value and
+// error), so that 2 f, the leading term, is nearly exact.
 template <bool F3 = false>
 GCCD_HD inline double log(double x) {
     if (!(x > 0.0)) return x == 0.0 ? -INFINITY : NAN;  // also NaN for NaN
@@ -99,21 +128,17 @@ GCCD_HD inline double log(double x) {
     const double num = m - 1.0;             // exact
     const double den = m + 1.0;             // rounded
     const double den_lo = m - (den - 1.0);  // m + 1 - den, exact
-    const double y = 1.0 / den;
+    const double y = recip(den);
     const double f = num * y;
     const double f_lo = (fma(-f, den, num) - f * den_lo) * y;
     const double s = f * f;
-    double q = 0.08695652173913043;  // 2/23
-    q = horner<F3>(q, s, 0.09523809523809523);
-    q = horner<F3>(q, s, 0.10526315789473684);
-    q = horner<F3>(q, s, 0.11764705882352941);
-    q = horner<F3>(q, s, 0.13333333333333333);
-    q = horner<F3>(q, s, 0.15384615384615385);
-    q = horner<F3>(q, s, 0.18181818181818182);
-    q = horner<F3>(q, s, 0.2222222222222222);
-    q = horner<F3>(q, s, 0.2857142857142857);
-    q = horner<F3>(q, s, 0.4);
-    q = horner<F3>(q, s, 0.6666666666666666);  // 2/3
+    double q = 0.14616451042434167;
+    q = horner<F3>(q, s, 0.15331721490738642);
+    q = horner<F3>(q, s, 0.18182889128565508);
+    q = horner<F3>(q, s, 0.22222211134749734);
+    q = horner<F3>(q, s, 0.28571428625975764);
+    q = horner<F3>(q, s, 0.39999999999899505);
+    q = horner<F3>(q, s, 0.666666666666667);
     const double de = (double)e;
     const double lo = fma(de, kLn2Lo, fma(f * s, q, 2.0 * f_lo));
     return fma(de, kLn2Hi, 2.0 * f) + lo;
@@ -127,34 +152,32 @@ GCCD_HD inline double log1p(double y) {
     if (u == 1.0) return y;
     if (u == INFINITY || u != u) return u;
     const double d = y - (u - 1.0);
-    return log<F3>(u) + d / u;
+    return log<F3>(u) + d * recip(u);
 }
 
 // sin(pi x) and cos(pi x) for finite x with |x| < 2^51: x = n/2 + r
-// (exact), |r| <= 1/4, the series of sin(pi r) to r^17 and cos(pi r) to
-// r^16, then the quadrant n mod 4.
+// (exact), |r| <= 1/4, sin(pi r) = r P(r^2) and cos(pi r) = C(r^2) with
+// near-minimax P and C of degrees 6 and 7 in r^2 (relative errors 3.9e-17
+// and 2.1e-17), then the quadrant n mod 4.
 template <bool F3 = false>
 GCCD_HD inline void sincospi(double x, double* sp, double* cp) {
     const double n = rint(2.0 * x);
     const double r = fma(-0.5, n, x);
     const double z = r * r;
-    double ps = 7.952054001475513e-07;  // pi^17/17!
-    ps = horner<F3>(ps, z, -2.1915353447830217e-05);
-    ps = horner<F3>(ps, z, 0.00046630280576761255);
-    ps = horner<F3>(ps, z, -0.0073704309457143504);
-    ps = horner<F3>(ps, z, 0.08214588661112823);
-    ps = horner<F3>(ps, z, -0.5992645293207921);
-    ps = horner<F3>(ps, z, 2.5501640398773455);
-    ps = horner<F3>(ps, z, -5.16771278004997);
+    double ps = 0.000461531855383581;
+    ps = horner<F3>(ps, z, -0.007370021586907771);
+    ps = horner<F3>(ps, z, 0.08214586918000175);
+    ps = horner<F3>(ps, z, -0.5992645289396449);
+    ps = horner<F3>(ps, z, 2.5501640398733763);
+    ps = horner<F3>(ps, z, -5.167712780049954);
     ps = horner<F3>(ps, z, 3.141592653589793);
     const double s = r * ps;
-    double pc = 4.303069587032947e-06;  // pi^16/16!
-    pc = horner<F3>(pc, z, -0.0001046381049248457);
-    pc = horner<F3>(pc, z, 0.0019295743094039231);
-    pc = horner<F3>(pc, z, -0.02580689139001406);
-    pc = horner<F3>(pc, z, 0.2353306303588932);
-    pc = horner<F3>(pc, z, -1.3352627688545895);
-    pc = horner<F3>(pc, z, 4.0587121264167685);
+    double pc = -0.00010356747255199479;
+    pc = horner<F3>(pc, z, 0.0019294657440800042);
+    pc = horner<F3>(pc, z, -0.025806885652951306);
+    pc = horner<F3>(pc, z, 0.23533063019088787);
+    pc = horner<F3>(pc, z, -1.3352627688519174);
+    pc = horner<F3>(pc, z, 4.058712126416747);
     pc = horner<F3>(pc, z, -4.934802200544679);
     const double c = fma(pc, z, 1.0);
     const int q = (int)((int64_t)n & 3);

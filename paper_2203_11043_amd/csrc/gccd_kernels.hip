@@ -1842,10 +1842,9 @@ __device__ __forceinline__ void build_small_list(const StepArgs& a) {
 
 // The FP64 functions of the step (gccd_fp64.h).  Carrier mode (no
 // repulsion) is bound by VALU issue and takes the three-operand Horner steps
-// (4.7e10 against 4.2e10 carrier-steps/s at 2^24 holes); list mode, which
-// streams the partial sums, the compiler's own (114 against 139 VGPRs).
-// Against the device library's versions: 26.7 against 27.1 us per list step
-// at 1e5 holes, 1.97 against 2.08 ms at the 4096-cloud batch.
+// (one instruction fewer per step, at the cost of registers); list mode,
+// which streams the partial sums, the compiler's own form, which needs
+// fewer registers.
 template <bool LIST>
 __device__ __forceinline__ double exp_s(double x) {
     return fp64::exp<!LIST>(x);
@@ -1998,8 +1997,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 if (a.diffusion) {
                     uint32_t w0 = local, w1 = step, w2 = a.event0 + e, w3 = 0u;
                     philox4x32_10(w0, w1, w2, w3, a.key0, a.key1);
-                    const double r01 = sqrt(-2.0 * log_s<LIST>(unit_open(w0)));
-                    const double r23 = sqrt(-2.0 * log_s<LIST>(unit_open(w2)));
+                    // -2 ln u > 2^-33 for u on the open grid (w + 1/2) 2^-32
+                    const double r01 = fp64::sqrt_pos(-2.0 * log_s<LIST>(unit_open(w0)));
+                    const double r23 = fp64::sqrt_pos(-2.0 * log_s<LIST>(unit_open(w2)));
                     // the angles 2 pi u in half-turns: 2 u is exact, and one
                     // argument reduction serves both sine and cosine
                     double s1, c1, s3, c3;
@@ -2007,7 +2007,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                     sincospi_s<LIST>(2.0 * unit_open(w3), &s3, &c3);
                     (void)s3;
                     const double D = a.vt * mu;                        // Eq. (4), cm^2/s
-                    const double sigma = sqrt(2.0 * D * a.dt_s) * 1e4;  // Eq. (3), um
+                    const double s2 = 2.0 * D * a.dt_s;
+                    const double sigma = (s2 > 0.0 ? fp64::sqrt_pos(s2) : 0.0) * 1e4;  // Eq. (3), um
                     dx += sigma * (r01 * c1);
                     dy += sigma * (r01 * s1);
                     dz += sigma * (r23 * c3);

@@ -1,12 +1,15 @@
-"""The step kernel's FP64 exp, log, log1p and sin/cos(pi x)
-(paper_2203_11043_amd/csrc/gccd_fp64.h), built for the host from the same
-source (only fma, frexp, ldexp, rint and IEEE division and comparison, so
-the host build computes what the device computes), against 40-digit
+"""The step kernel's FP64 exp, log, log1p, sin/cos(pi x), reciprocal and
+square root (paper_2203_11043_amd/csrc/gccd_fp64.h), built for the host from
+the same source (only fma, frexp, ldexp, rint and IEEE comparison; the
+reciprocal and square root start from a single-precision estimate where the
+device takes its hardware one, then the same Newton steps), against 40-digit
 references: at most 2 units in the last place over the
 arguments the time step gives them (Eq. (2): ln |E|^2, the exponent of
-(|E|/Ec)^beta, log1p of it; Box-Muller: ln u and the angles 2 u of
-u = (w + 1/2) 2^-32) and over the functions' whole ranges, plus the
-special values."""
+(|E|/Ec)^beta, log1p of it; Box-Muller: ln u, the angles 2 u of
+u = (w + 1/2) 2^-32 and sqrt(-2 ln u); Eq. (3): sqrt(2 D dt)) and over the
+functions' whole ranges (the reciprocal and square root over single
+precision's normal range, where the host estimate exists), plus the special
+values."""
 import os
 import subprocess
 
@@ -27,13 +30,15 @@ def run(tmp_path_factory):
     subprocess.run(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-I", INC, SRC, "-o", exe,
                     "-lm"], check=True)
 
-    def call(xe, xl, xp, xs):
+    def call(xe, xl, xp, xs, xr=None):
         n = len(xe)
-        inp = np.concatenate([xe, xl, xp, xs]).astype(np.float64)
+        if xr is None:
+            xr = np.ones(n)
+        inp = np.concatenate([xe, xl, xp, xs, xr]).astype(np.float64)
         fi, fo = str(d / "in.bin"), str(d / "out.bin")
         inp.tofile(fi)
         subprocess.run([exe, fi, fo, str(n)], check=True)
-        out = np.fromfile(fo, dtype=np.float64).reshape(5, n)
+        out = np.fromfile(fo, dtype=np.float64).reshape(7, n)
         return out
     return call
 
@@ -49,7 +54,10 @@ def args(n, seed):
                          2.0 ** rng.uniform(-1070.0, 1023.0, n - 2 * (n // 3))])
     xp = 10.0 ** rng.uniform(-20.0, 6.0, n)                           # (|E|/Ec)^beta
     xs = np.concatenate([2.0 * u[: n // 2], rng.uniform(-8.0, 8.0, n - n // 2)])
-    return xe, xl, xp, xs
+    xr = np.concatenate([-2.0 * np.log(u[: n // 3]),                  # Box-Muller radius^2
+                         10.0 ** rng.uniform(-14.0, -6.0, n // 3),    # 2 D dt in cm^2
+                         10.0 ** rng.uniform(-37.0, 38.0, n - 2 * (n // 3))])
+    return xe, xl, xp, xs, xr
 
 
 def ulp_error(got, ref):
@@ -65,15 +73,17 @@ def ulp_error(got, ref):
 def test_against_40_digit_references(run):
     mp.mp.dps = 40
     n = 6000
-    xe, xl, xp, xs = args(n, 5)
-    out = run(xe, xl, xp, xs)
+    xe, xl, xp, xs, xr = args(n, 5)
+    out = run(xe, xl, xp, xs, xr)
     worst = {}
     for name, xs_, refs, k, bound in (
             ("exp", xe, lambda x: mp.exp(x), 0, 2.0),
             ("log", xl, lambda x: mp.log(x), 1, 2.0),
             ("log1p", xp, lambda x: mp.log1p(x), 2, 2.0),
             ("sinpi", xs, lambda x: mp.sinpi(x), 3, 2.0),
-            ("cospi", xs, lambda x: mp.cospi(x), 4, 2.0)):
+            ("cospi", xs, lambda x: mp.cospi(x), 4, 2.0),
+            ("recip", xr, lambda x: 1 / x, 5, 1.0),
+            ("sqrt", xr, lambda x: mp.sqrt(x), 6, 1.0)):
         errs = [ulp_error(out[k][i], refs(mp.mpf(float(xs_[i])))) for i in range(n)]
         worst[name] = max(errs)
         print(f"[fp64] {name}: max {worst[name]:.2f} ulp over {n} arguments", flush=True)
@@ -87,8 +97,10 @@ def test_special_values(run):
                    0.7071067811865476, 1.4142135623730951])
     xp = np.array([0.0, 1e-300, 1e-17, inf, nan, 1.0, -0.5, 1e300, 2.0**-53, 2.0**-52, 3.0, 1e6])
     xs = np.array([0.0, 0.25, 0.5, 0.75, 1.0, 1.25, 1.5, 1.75, 2.0, -0.5, 4.0, 1e-20])
-    out = run(xe, xl, xp, xs)
-    e, l, p, s, c = out
+    xr = np.array([1.0, 4.0, 2.0, 0.25, 1.7, 2.414213562373095, 3.0, 1e-30, 1e30, 2.0**-126,
+                   2.0**126, 1.0 - 2.0**-53])
+    out = run(xe, xl, xp, xs, xr)
+    e, l, p, s, c, rc, sq = out
     assert e[0] == 1.0 and e[1] == 1.0 and e[4] == inf and e[5] == 0.0 and np.isnan(e[6])
     assert e[9] == inf and e[10] == 0.0 and e[11] == 1.0
     assert np.isfinite(e[7]) and e[8] > 0.0
@@ -102,3 +114,7 @@ def test_special_values(run):
     assert list(c[[0, 2, 4, 6, 8]]) == [1.0, 0.0, -1.0, 0.0, 1.0]
     assert abs(s[1] - np.sqrt(0.5)) <= 2e-16 and abs(c[1] - np.sqrt(0.5)) <= 2e-16
     assert s[9] == -1.0 and s[10] == 0.0 and c[10] == 1.0 and s[11] == np.pi * 1e-20
+    # exact squares and powers of two give exact results
+    assert list(rc[[0, 1, 2, 3]]) == [1.0, 0.25, 0.5, 4.0] and rc[9] == 2.0**126
+    assert list(sq[[0, 1, 3]]) == [1.0, 2.0, 0.5] and sq[9] == 2.0**-63 and sq[10] == 2.0**63
+    assert abs(sq[2] - np.sqrt(2.0)) <= 2.3e-16 and abs(sq[6] - np.sqrt(3.0)) <= 2.3e-16

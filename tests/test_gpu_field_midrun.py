@@ -155,3 +155,51 @@ def test_field_batch_after_100_steps(g, W, orc):
           f"({part_collected} partly collected): max|dE|/A = {worst_a:.3e}, "
           f"max|dE|/rms|E| = {worst_r:.3e}", flush=True)
     assert worst_a <= FIELD_TOL and worst_r <= FIELD_TOL
+
+
+def test_field_muon_track_after_600_steps(g, W, orc):
+    """The muon track (62 354 holes over the full thickness) after 600
+    steps: the holes near the front surface collected and frozen as
+    sources, the rest spread by repulsion; 256 sampled holes (travelling and
+    collected) against all sources."""
+    w = W.muon_track(seed=1)
+    d = dict(W.DEVICE)
+    pos, cs, E, done, na = run_then_field(g, d, w.x, w.y, w.z, w.dt_ps, steps=600)
+    assert done == 600 and 0 < na < w.n
+    idx = np.random.default_rng(600).choice(w.n, 256, replace=False)
+    Eo, A = orc.field([pos[0, idx], pos[1, idx], pos[2, idx]], [pos[0], pos[1], pos[2]],
+                      with_magnitude=True)
+    ea, er = errors(E[:, idx], Eo, A)
+    print(f"[midrun] muon track after 600 steps ({na} travelling): max|dE|/A = {ea:.3e}, "
+          f"max|dE|/rms|E| = {er:.3e}", flush=True)
+    assert ea <= FIELD_TOL and er <= FIELD_TOL
+
+
+def test_run_split_across_the_pipelining_switch(g, W):
+    """A 1e5-hole cloud 60 um deep: its pair work per step (travelling
+    holes times all holes) starts at 1e10 and falls below the level from
+    which the list is sorted on a second stream while the field runs (5e9
+    pairs) before every hole is collected (about 240 steps), so the run
+    switches from the pipelined to the serial list at a step that is a
+    multiple of 32.  The same run in one call of up to 256 steps and in
+    calls of 50, 70 and 136 steps (the third ending where the cloud is
+    gone) gives the same positions and collection steps bit for bit."""
+    w = W.single_cloud(100000, seed=2, depth_um=60.0)
+    out = []
+    for parts in ([256], [50, 70, 136]):
+        ctx = g.gccd_init(g.Params.from_device(dict(W.DEVICE)))
+        try:
+            g.gccd_load(ctx, *gpu(w.x, w.y, w.z))
+            done = 0
+            for k in parts:
+                done += g.gccd_run(ctx, w.dt_ps, k)[0]
+            pos, cs = g.gccd_positions(ctx, w.n)
+            out.append((done, pos.cpu().numpy(), cs.cpu().numpy(),
+                        g.gccd_stats(ctx)["n_active"]))
+        finally:
+            g.gccd_destroy(ctx)
+    (d1, p1, c1, a1), (d2, p2, c2, a2) = out
+    print(f"[midrun] 1e5 at 60 um: {d1} and {d2} steps, {a1} travelling at the end "
+          f"({a1 * 1e5:.2e} pairs per step)", flush=True)
+    assert d1 == d2 and 120 < d1 <= 256 and a1 == a2 and a1 * 100000 < 4e9
+    assert np.array_equal(p1, p2) and np.array_equal(c1, c2)
