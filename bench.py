@@ -154,7 +154,7 @@ def closure_leg(gccd, workloads, torch, n: int = 1000000, seed: int = 2000,
     return out
 
 
-DRIFT_BYTES_PER_CARRIER_STEP = 56   # x, y, z read and written (48), collection step and event read (8)
+DRIFT_BYTES_PER_CARRIER_STEP = 52   # x, y, z read and written (48), collection step read (4); a single event's carriers need no event read
 
 
 def drift_leg(gccd, workloads, torch, n: int, steps: int, warm: int, cpu: bool) -> dict:

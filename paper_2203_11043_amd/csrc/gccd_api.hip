@@ -1411,6 +1411,7 @@ int gccd_run(gccd_ctx* c, double dt_ps, int64_t max_steps, int64_t* steps_done,
     sa.sources_all = c->p.collected_are_sources;
     sa.ev_chunks = c->ev_chunks_d;
     sa.ev_of = c->ev_of;
+    sa.one_event = c->n_events == 1 ? 1 : 0;
     sa.kl = c->kl;
     sa.part = c->part;
     sa.pstride = n;

@@ -84,14 +84,12 @@ constexpr double kLn2Lo = 0x1.ef35793c76730p-45;
 constexpr double kLog2E = 1.4426950408889634;  // 1 / ln 2
 constexpr double kSqrtHalf = 0.7071067811865476;
 
-// e^x.  x = k ln 2 + r, |r| <= ln 2 / 2 (Cody-Waite reduction with the
-// split ln 2; the first product is exact), e^r by a degree-11 polynomial
-// (relative error 1.7e-17 on the interval), times 2^k.
+// e^x for x in [-745.2, 709.8] (no special cases).  x = k ln 2 + r,
+// |r| <= ln 2 / 2 (Cody-Waite reduction with the split ln 2; the first
+// product is exact), e^r by a degree-11 polynomial (relative error 1.7e-17
+// on the interval), times 2^k.
 template <bool F3 = false>
-GCCD_HD inline double exp(double x) {
-    if (x != x) return x;
-    if (x > 709.8) return INFINITY;
-    if (x < -745.2) return 0.0;
+GCCD_HD inline double exp_fin(double x) {
     const double k = rint(x * kLog2E);
     const double r = fma(-k, kLn2Lo, fma(-k, kLn2Hi, x));
     double p = 2.5110037721946562e-08;
@@ -109,16 +107,25 @@ GCCD_HD inline double exp(double x) {
     return ldexp(p, (int)k);
 }
 
-// ln x.  x = 2^e m with m in [sqrt(1/2), sqrt(2)); ln m = 2 atanh(f),
-// f = (m - 1)/(m + 1), |f| <= 0.1716, taken as 2 f + f s q(s), s = f^2, with
-// q a degree-6 polynomial (relative error 4.7e-16 in a term below 1 % of
-// the sum); ln x = e ln 2 + ln m.  f is carried as f + f_lo (the residual
-// of the division, with m + 1 split exactly into its rounded value and
-// error), so that 2 f, the leading term, is nearly exact.
+// e^x with the special values: NaN for NaN, +inf above 709.8, 0 below
+// -745.2.
 template <bool F3 = false>
-GCCD_HD inline double log(double x) {
-    if (!(x > 0.0)) return x == 0.0 ? -INFINITY : NAN;  // also NaN for NaN
-    if (x == INFINITY) return x;
+GCCD_HD inline double exp(double x) {
+    if (x != x) return x;
+    if (x > 709.8) return INFINITY;
+    if (x < -745.2) return 0.0;
+    return exp_fin<F3>(x);
+}
+
+// ln x for finite x > 0.  x = 2^e m with m in [sqrt(1/2), sqrt(2));
+// ln m = 2 atanh(f), f = (m - 1)/(m + 1), |f| <= 0.1716, taken as
+// 2 f + f s q(s), s = f^2, with q a degree-6 polynomial (relative error
+// 4.7e-16 in a term below 1 % of the sum); ln x = e ln 2 + ln m.  f is
+// carried as f + f_lo (the residual of the division, with m + 1 split
+// exactly into its rounded value and error), so that 2 f, the leading term,
+// is nearly exact.
+template <bool F3 = false>
+GCCD_HD inline double log_pos(double x) {
     int e;
     double m = frexp(x, &e);  // m in [1/2, 1)
     if (m < kSqrtHalf) {
@@ -144,8 +151,28 @@ GCCD_HD inline double log(double x) {
     return fma(de, kLn2Hi, 2.0 * f) + lo;
 }
 
-// ln(1 + y), y >= -1: u = 1 + y rounded, d = y - (u - 1) its rounding error
-// (exact), ln(1 + y) = ln u + d / u to first order in d / u.
+// ln x with the special values: -inf at 0, NaN below 0 and for NaN, +inf
+// at +inf.
+template <bool F3 = false>
+GCCD_HD inline double log(double x) {
+    if (!(x > 0.0)) return x == 0.0 ? -INFINITY : NAN;  // also NaN for NaN
+    if (x == INFINITY) return x;
+    return log_pos<F3>(x);
+}
+
+// ln(1 + y) for finite y > -1 with 1 + y finite (no special cases): u = 1 + y
+// rounded, d = y - (u - 1) its rounding error (exact), ln(1 + y) =
+// ln u + d / u to first order in d / u.  Where u rounds to 1, ln u is 0 and
+// the result is y.
+template <bool F3 = false>
+GCCD_HD inline double log1p_fin(double y) {
+    const double u = 1.0 + y;
+    const double d = y - (u - 1.0);
+    return log_pos<F3>(u) + d * recip(u);
+}
+
+// ln(1 + y), y >= -1, with the special values (-inf at -1, +inf at +inf,
+// NaN for NaN).
 template <bool F3 = false>
 GCCD_HD inline double log1p(double y) {
     const double u = 1.0 + y;

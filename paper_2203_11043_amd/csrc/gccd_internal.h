@@ -109,6 +109,8 @@ struct StepArgs {
                                // (0) the ev_active travelling holes
     const int32_t* ev_chunks;  // [E] chunks of each event's field sum (list mode)
     const uint32_t* ev_of;     // [n] event of each carrier (carrier mode)
+    int32_t one_event;         // 1: a single event (offset 0, every carrier), whose
+                               // offsets and carrier events need not be read
     KeyLayout kl;
     const float* part;
     uint32_t pstride;

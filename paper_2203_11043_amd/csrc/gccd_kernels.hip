@@ -1846,16 +1846,16 @@ __device__ __forceinline__ void build_small_list(const StepArgs& a) {
 // which streams the partial sums, the compiler's own form, which needs
 // fewer registers.
 template <bool LIST>
-__device__ __forceinline__ double exp_s(double x) {
-    return fp64::exp<!LIST>(x);
+__device__ __forceinline__ double exp_fin_s(double x) {
+    return fp64::exp_fin<!LIST>(x);
 }
 template <bool LIST>
-__device__ __forceinline__ double log_s(double x) {
-    return fp64::log<!LIST>(x);
+__device__ __forceinline__ double log_pos_s(double x) {
+    return fp64::log_pos<!LIST>(x);
 }
 template <bool LIST>
-__device__ __forceinline__ double log1p_s(double x) {
-    return fp64::log1p<!LIST>(x);
+__device__ __forceinline__ double log1p_fin_s(double x) {
+    return fp64::log1p_fin<!LIST>(x);
 }
 template <bool LIST>
 __device__ __forceinline__ void sincospi_s(double x, double* s, double* c) {
@@ -1896,8 +1896,16 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 // still holds the holes collected in the last step): the
                 // carrier's own collection step decides
                 key = a.keys_in[slot];
-                e = key_event(key, a.kl);
-                const uint32_t off = a.ev_off[e], ne = a.ev_off[e + 1] - off;
+                uint32_t off, ne;
+                if (a.one_event) {
+                    e = 0u;
+                    off = 0u;
+                    ne = a.n_all;
+                } else {
+                    e = key_event(key, a.kl);
+                    off = a.ev_off[e];
+                    ne = a.ev_off[e + 1] - off;
+                }
                 local = min(key_local(key, a.kl), ne - 1u);
                 j = off + local;
                 active = a.cstep[j] < 0;
@@ -1913,8 +1921,13 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 }
             } else {
                 j = slot;
-                e = a.ev_of[j];
-                local = j - a.ev_off[e];
+                if (a.one_event) {
+                    e = 0u;
+                    local = j;
+                } else {
+                    e = a.ev_of[j];
+                    local = j - a.ev_off[e];
+                }
                 active = a.cstep[j] < 0;
             }
             if (active) {
@@ -1979,27 +1992,34 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 }
                 const double x0 = a.x[j], y0 = a.y[j], z0 = a.z[j];
                 const double es = a.a1 * z0 - a.a2;
-                const double ex = ecx, ey = ecy, ez = ecz + es;
+                const double ex = ecx, ey = ecy, ez = LIST ? ecz + es : es;
                 double mu = a.mu0;
                 if (a.mobility_model == 0) {
                     // Eq. (2), mu0 / (1 + (|E|/Ec)^beta)^(1/beta), as
                     // mu0 exp(-log1p(y) / beta) with y = exp(beta (log|E|^2 / 2
                     // - log Ec)): four transcendentals instead of two general
-                    // powers and a square root (|E| = 0 gives y = 0, mu = mu0)
-                    const double y =
-                        exp_s<LIST>(a.beta * (0.5 * log_s<LIST>(ex * ex + ey * ey + ez * ez) - a.log_ec));
-                    mu = a.mu0 * exp_s<LIST>(-a.inv_beta * log1p_s<LIST>(y));
+                    // powers and a square root.  The arguments are held in the
+                    // functions' finite ranges, so no special case is tested:
+                    // |E|^2 at or above 2^-1000 (|E| = 0 then gives a y far
+                    // below the rounding of 1 + y, so mu = mu0 exactly, as
+                    // y = 0 would), the exponents within [-745, 709]
+                    const double e2 = fmax(ex * ex + ey * ey + ez * ez, 0x1p-1000);
+                    const double ly = a.beta * (0.5 * log_pos_s<LIST>(e2) - a.log_ec);
+                    const double y = exp_fin_s<LIST>(fmin(fmax(ly, -745.0), 709.0));
+                    mu = a.mu0 * exp_fin_s<LIST>(fmax(-a.inv_beta * log1p_fin_s<LIST>(y), -745.0));
                 }
-                // v = mu E in cm/s; v dt in cm; 1 cm = 1e4 um
-                double dx = mu * ex * a.dt_s * 1e4;
-                double dy = mu * ey * a.dt_s * 1e4;
+                // v = mu E in cm/s; v dt in cm; 1 cm = 1e4 um.  Without
+                // repulsion the field is the static one, along z only: no
+                // lateral drift (mu 0 dt = +0 exactly)
+                double dx = LIST ? mu * ex * a.dt_s * 1e4 : 0.0;
+                double dy = LIST ? mu * ey * a.dt_s * 1e4 : 0.0;
                 double dz = mu * ez * a.dt_s * 1e4;
                 if (a.diffusion) {
                     uint32_t w0 = local, w1 = step, w2 = a.event0 + e, w3 = 0u;
                     philox4x32_10(w0, w1, w2, w3, a.key0, a.key1);
                     // -2 ln u > 2^-33 for u on the open grid (w + 1/2) 2^-32
-                    const double r01 = fp64::sqrt_pos(-2.0 * log_s<LIST>(unit_open(w0)));
-                    const double r23 = fp64::sqrt_pos(-2.0 * log_s<LIST>(unit_open(w2)));
+                    const double r01 = fp64::sqrt_pos(-2.0 * log_pos_s<LIST>(unit_open(w0)));
+                    const double r23 = fp64::sqrt_pos(-2.0 * log_pos_s<LIST>(unit_open(w2)));
                     // the angles 2 pi u in half-turns: 2 u is exact, and one
                     // argument reduction serves both sine and cosine
                     double s1, c1, s3, c3;
@@ -2007,8 +2027,11 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                     sincospi_s<LIST>(2.0 * unit_open(w3), &s3, &c3);
                     (void)s3;
                     const double D = a.vt * mu;                        // Eq. (4), cm^2/s
-                    const double s2 = 2.0 * D * a.dt_s;
-                    const double sigma = (s2 > 0.0 ? fp64::sqrt_pos(s2) : 0.0) * 1e4;  // Eq. (3), um
+                    // Eq. (3), um; 2 D dt > 0 (T > 0, dt > 0), held at or
+                    // above 2^-1000 so that the square root's estimate stays
+                    // in range even for a dt that underflows it
+                    const double s2 = fmax(2.0 * D * a.dt_s, 0x1p-1000);
+                    const double sigma = fp64::sqrt_pos(s2) * 1e4;
                     dx += sigma * (r01 * c1);
                     dy += sigma * (r01 * s1);
                     dz += sigma * (r23 * c3);

@@ -9,7 +9,8 @@ arguments the time step gives them (Eq. (2): ln |E|^2, the exponent of
 u = (w + 1/2) 2^-32 and sqrt(-2 ln u); Eq. (3): sqrt(2 D dt)) and over the
 functions' whole ranges (the reciprocal and square root over single
 precision's normal range, where the host estimate exists), plus the special
-values."""
+values.  The forms without special-case tests that the step takes (exp_fin,
+log1p_fin) equal the full ones bit for bit in their ranges."""
 import os
 import subprocess
 
@@ -38,7 +39,7 @@ def run(tmp_path_factory):
         fi, fo = str(d / "in.bin"), str(d / "out.bin")
         inp.tofile(fi)
         subprocess.run([exe, fi, fo, str(n)], check=True)
-        out = np.fromfile(fo, dtype=np.float64).reshape(7, n)
+        out = np.fromfile(fo, dtype=np.float64).reshape(9, n)
         return out
     return call
 
@@ -83,7 +84,9 @@ def test_against_40_digit_references(run):
             ("sinpi", xs, lambda x: mp.sinpi(x), 3, 2.0),
             ("cospi", xs, lambda x: mp.cospi(x), 4, 2.0),
             ("recip", xr, lambda x: 1 / x, 5, 1.0),
-            ("sqrt", xr, lambda x: mp.sqrt(x), 6, 1.0)):
+            ("sqrt", xr, lambda x: mp.sqrt(x), 6, 1.0),
+            ("exp_fin", xe, lambda x: mp.exp(x), 7, 2.0),
+            ("log1p_fin", xp, lambda x: mp.log1p(x), 8, 2.0)):
         errs = [ulp_error(out[k][i], refs(mp.mpf(float(xs_[i])))) for i in range(n)]
         worst[name] = max(errs)
         print(f"[fp64] {name}: max {worst[name]:.2f} ulp over {n} arguments", flush=True)
@@ -100,7 +103,7 @@ def test_special_values(run):
     xr = np.array([1.0, 4.0, 2.0, 0.25, 1.7, 2.414213562373095, 3.0, 1e-30, 1e30, 2.0**-126,
                    2.0**126, 1.0 - 2.0**-53])
     out = run(xe, xl, xp, xs, xr)
-    e, l, p, s, c, rc, sq = out
+    e, l, p, s, c, rc, sq, ef, pf = out
     assert e[0] == 1.0 and e[1] == 1.0 and e[4] == inf and e[5] == 0.0 and np.isnan(e[6])
     assert e[9] == inf and e[10] == 0.0 and e[11] == 1.0
     assert np.isfinite(e[7]) and e[8] > 0.0
@@ -118,3 +121,10 @@ def test_special_values(run):
     assert list(rc[[0, 1, 2, 3]]) == [1.0, 0.25, 0.5, 4.0] and rc[9] == 2.0**126
     assert list(sq[[0, 1, 3]]) == [1.0, 2.0, 0.5] and sq[9] == 2.0**-63 and sq[10] == 2.0**63
     assert abs(sq[2] - np.sqrt(2.0)) <= 2.3e-16 and abs(sq[6] - np.sqrt(3.0)) <= 2.3e-16
+    # the forms without special cases agree with the full ones in their ranges
+    # (exp_fin on [-745.2, 709.8], log1p_fin on finite y > -1, where 1 + y
+    # rounding to 1 gives y itself)
+    fin = (xe >= -745.2) & (xe <= 709.8)
+    assert np.array_equal(ef[fin], e[fin])
+    fin = np.isfinite(xp) & (xp > -1.0)
+    assert np.array_equal(pf[fin], p[fin])
