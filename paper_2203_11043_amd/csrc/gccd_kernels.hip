@@ -1723,8 +1723,10 @@ __device__ __forceinline__ double unit_open(uint32_t w) {
 //     atomic per wave.
 // ---------------------------------------------------------------------------
 // The list of a load of at most kFusedList carriers in at most kFusedTiles
-// source tiles, rebuilt by the last workgroup of its step: the new keys
-// sorted in LDS (bitonic_sort_lanes), each event's travelling holes (its
+// source tiles, rebuilt by the last workgroup of its step: the new keys,
+// which each workgroup of the step left as a sorted run of its slots
+// (sort_block_keys), merged in LDS (merge_sorted_runs), each event's
+// travelling holes (its
 // first collected key, by binary search in LDS), and the positions and
 // boxes of every source tile in slot order -- the same list, counts, slots
 // and boxes as sort_keys, count_active and gather_tiles.  Wave w gathers
@@ -1739,10 +1741,11 @@ __device__ __forceinline__ void build_small_list(const StepArgs& a) {
     __shared__ uint32_t act[kFusedList];
     __shared__ double qbox[kFusedTiles][4][6];
     const uint32_t n = a.n_all;
+    // the step's workgroups left sorted runs of kStepThreads keys
     if (n <= (uint32_t)kFusedList / 2)
-        bitonic_sort_lanes<kFusedList / 2 / kStepThreads>(a.keys_out, n, s);
+        merge_sorted_runs<kFusedList / 2 / kSortItems>(a.keys_out, n, s, kStepThreads);
     else
-        bitonic_sort_lanes<kFusedList / kStepThreads>(a.keys_out, n, s);
+        merge_sorted_runs<kFusedList / kSortItems>(a.keys_out, n, s, kStepThreads);
     for (uint32_t i = threadIdx.x; i < n; i += kStepThreads) a.keys_sorted[i] = s[lds_slot(i)];
     for (uint32_t e = threadIdx.x; e < a.n_events; e += kStepThreads) {
         const uint32_t off = a.ev_off[e], ne = a.ev_off[e + 1] - off;
@@ -1883,6 +1886,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
     const int lane = threadIdx.x & 63;
     uint32_t kept = 0;  // this wave's holes still travelling (wave-uniform)
     unsigned long long pairs = 0;  // this lane's pair interactions of Eq. (6)
+    uint64_t run_key = ~0ull;      // FUSE: this slot's new key (one slot per thread)
     for (uint32_t base = blockIdx.x * kStepThreads; base < a.n_all;
          base += gridDim.x * kStepThreads) {
         const uint32_t slot = base + threadIdx.x;
@@ -1939,9 +1943,24 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                     const float* pp = a.part + slot;
                     const size_t ps = a.pstride;
                     int c = 0;
-                    // eight, then four groups' loads in flight ahead of their adds
-                    // (the adds in group order)
-                    for (; c + 8 <= nchunk; c += 8) {
+                    // eight (a small load, latency-bound: sixteen), then four
+                    // groups' loads in flight ahead of their adds (the adds in
+                    // group order)
+                    constexpr int kW = FUSE ? 16 : 8;
+                    for (; c + kW <= nchunk; c += kW) {
+                        float v[kW][3];
+#pragma unroll
+                        for (int u = 0; u < kW; ++u)
+#pragma unroll
+                            for (int d = 0; d < 3; ++d) v[u][d] = pp[(size_t)((c + u) * 3 + d) * ps];
+#pragma unroll
+                        for (int u = 0; u < kW; ++u) {
+                            sx += (double)v[u][0];
+                            sy += (double)v[u][1];
+                            sz += (double)v[u][2];
+                        }
+                    }
+                    if (FUSE && c + 8 <= nchunk) {
                         float v[8][3];
 #pragma unroll
                         for (int u = 0; u < 8; ++u)
@@ -1953,6 +1972,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                             sy += (double)v[u][1];
                             sz += (double)v[u][2];
                         }
+                        c += 8;
                     }
                     for (; c + 4 <= nchunk; c += 4) {
                         float v[4][3];
@@ -2048,7 +2068,10 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 keep = !collected;
                 if (LIST) key = make_key(e, collected, xn, yn, zn, local, a.kl);
             }
-            if (LIST) a.keys_out[slot] = key;
+            if constexpr (FUSE)
+                run_key = key;
+            else if (LIST)
+                a.keys_out[slot] = key;
         }
         kept += (uint32_t)__popcll(__ballot(keep));
     }
@@ -2074,6 +2097,15 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
         if (pr && a.coulomb) atomicAdd(&a.stats[1], pr);
     }
     if constexpr (FUSE) {
+        // the workgroup's slots (one per thread) leave their new keys as a
+        // sorted run of kStepThreads, which the list rebuild merges with the
+        // others
+        {
+            __shared__ uint64_t sk[kStepThreads];
+            const uint64_t sorted = sort_block_keys(run_key, sk);
+            const uint32_t pos = blockIdx.x * kStepThreads + threadIdx.x;
+            if (pos < a.n_all) a.keys_out[pos] = sorted;
+        }
         // the last workgroup to arrive rebuilds the list: each thread's
         // stores of the step are made visible at device scope before its
         // workgroup arrives, and the last one sees every workgroup's
@@ -2105,7 +2137,8 @@ hipError_t launch_step(const StepArgs& a, uint32_t n_slots, hipStream_t s) {
         if (!a.list_mode || n_slots != a.n_all || n_slots > (uint32_t)kFusedList ||
             a.n_tiles > (uint32_t)kFusedTiles)
             return hipErrorInvalidValue;
-        step_update<true><<<grid_for(n_slots, kStepThreads, 16384), kStepThreads, 0, s>>>(a);
+        // one slot per thread: workgroup b's keys are slots [b, b + 1) kStepThreads
+        step_update<true><<<(n_slots + kStepThreads - 1) / kStepThreads, kStepThreads, 0, s>>>(a);
     } else if (a.list_mode) {
         step_update<false><<<grid_for(n_slots, kStepThreads, 16384), kStepThreads, 0, s>>>(a);
     } else {

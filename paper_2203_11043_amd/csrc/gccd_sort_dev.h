@@ -33,29 +33,16 @@ __device__ __forceinline__ void register_sort(uint64_t (&v)[kSortItems]) {
                 if ((e & j) == 0u) compare_exchange(v[e], v[e | j], (e & k) == 0u);
 }
 
-// Sorts in[0, cnt) (cnt <= T = THREADS * kSortItems) into s[lds_slot(i)],
-// i < T, padded with ~0 (a key equal to the padding value is the same
-// value).  Each of the first THREADS lanes sorts kSortItems consecutive keys
-// in registers, then log2(T / kSortItems) levels merge pairs of sorted runs
-// in LDS, each lane writing kSortItems consecutive outputs of its pair
-// (found by a binary search on the merge path, then a sequential merge).
-// Every level moves each key once through LDS.  Every thread of the
-// workgroup calls it (lanes from THREADS on only pass the barriers); s holds
-// T + T / kSortItems words; it ends with a barrier.
+// The merge levels of block_sort_lds from sorted runs of w0 keys (a power
+// of two, at least kSortItems): lane t of the first THREADS holds positions
+// t kSortItems .. t kSortItems + kSortItems - 1 in v; the sorted T keys end
+// in s[lds_slot(i)], followed by a barrier.
 template <int THREADS>
-__device__ __forceinline__ void block_sort_lds(const uint64_t* in, uint32_t cnt, uint64_t* s) {
+__device__ __forceinline__ void merge_levels(uint64_t (&v)[kSortItems], uint64_t* s, uint32_t w0) {
     constexpr uint32_t T = (uint32_t)THREADS * kSortItems;
     const bool on = threadIdx.x < (uint32_t)THREADS;
     const uint32_t first = threadIdx.x * kSortItems;
-    for (uint32_t i = threadIdx.x; i < T; i += blockDim.x) s[lds_slot(i)] = i < cnt ? in[i] : ~0ull;
-    __syncthreads();
-    uint64_t v[kSortItems];
-    if (on) {
-#pragma unroll
-        for (uint32_t e = 0; e < (uint32_t)kSortItems; ++e) v[e] = s[lds_slot(first + e)];
-        register_sort(v);
-    }
-    for (uint32_t w = kSortItems; w < T; w <<= 1) {
+    for (uint32_t w = w0; w < T; w <<= 1) {
         __syncthreads();  // every read of s is done before it is written again
         if (on) {
 #pragma unroll
@@ -100,6 +87,50 @@ __device__ __forceinline__ void block_sort_lds(const uint64_t* in, uint32_t cnt,
     __syncthreads();
 }
 
+// Sorts in[0, cnt) (cnt <= T = THREADS * kSortItems) into s[lds_slot(i)],
+// i < T, padded with ~0 (a key equal to the padding value is the same
+// value).  Each of the first THREADS lanes sorts kSortItems consecutive keys
+// in registers, then log2(T / kSortItems) levels merge pairs of sorted runs
+// in LDS, each lane writing kSortItems consecutive outputs of its pair
+// (found by a binary search on the merge path, then a sequential merge).
+// Every level moves each key once through LDS.  Every thread of the
+// workgroup calls it (lanes from THREADS on only pass the barriers); s holds
+// T + T / kSortItems words; it ends with a barrier.
+template <int THREADS>
+__device__ __forceinline__ void block_sort_lds(const uint64_t* in, uint32_t cnt, uint64_t* s) {
+    constexpr uint32_t T = (uint32_t)THREADS * kSortItems;
+    const bool on = threadIdx.x < (uint32_t)THREADS;
+    const uint32_t first = threadIdx.x * kSortItems;
+    for (uint32_t i = threadIdx.x; i < T; i += blockDim.x) s[lds_slot(i)] = i < cnt ? in[i] : ~0ull;
+    __syncthreads();
+    uint64_t v[kSortItems];
+    if (on) {
+#pragma unroll
+        for (uint32_t e = 0; e < (uint32_t)kSortItems; ++e) v[e] = s[lds_slot(first + e)];
+        register_sort(v);
+    }
+    merge_levels<THREADS>(v, s, kSortItems);
+}
+
+// Merge of in[0, cnt) (cnt <= T = THREADS * kSortItems), whose runs of w0
+// keys (the last one possibly shorter) are each sorted, into s[lds_slot(i)],
+// i < T, padded with ~0.  Every thread of the workgroup calls it; it ends
+// with a barrier.
+template <int THREADS>
+__device__ __forceinline__ void merge_sorted_runs(const uint64_t* in, uint32_t cnt, uint64_t* s,
+                                                  uint32_t w0) {
+    constexpr uint32_t T = (uint32_t)THREADS * kSortItems;
+    const uint32_t first = threadIdx.x * kSortItems;
+    for (uint32_t i = threadIdx.x; i < T; i += blockDim.x) s[lds_slot(i)] = i < cnt ? in[i] : ~0ull;
+    __syncthreads();
+    uint64_t v[kSortItems];
+    if (threadIdx.x < (uint32_t)THREADS) {
+#pragma unroll
+        for (uint32_t e = 0; e < (uint32_t)kSortItems; ++e) v[e] = s[lds_slot(first + e)];
+    }
+    merge_levels<THREADS>(v, s, w0);
+}
+
 // 64-bit value of lane (this lane ^ m) of the wave: two LDS-crossbar
 // permutes with the byte index computed once.
 __device__ __forceinline__ uint64_t lane_xor(uint64_t v, uint32_t m) {
@@ -109,70 +140,28 @@ __device__ __forceinline__ uint64_t lane_xor(uint64_t v, uint32_t m) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Compare-exchange stage of a bitonic network at distance J < K inside each
-// lane's K keys (element i = lane_base + r ascends where (i & k) == 0).
-template <int K, int J>
-__device__ __forceinline__ void lane_stage(uint64_t (&v)[K], uint32_t base, uint32_t k) {
-#pragma unroll
-    for (uint32_t r = 0; r < (uint32_t)K; ++r)
-        if ((r & (uint32_t)J) == 0u) compare_exchange(v[r], v[r | J], ((base + r) & k) == 0u);
-}
-
-// Bitonic sort of in[0, n) (n <= T = blockDim.x * K, blockDim.x a multiple
-// of 64, T a power of two) into s[lds_slot(i)], i < T, padded with ~0, for
-// lists small enough that the latency of the network, not its work, sets
-// the time.  Lane t holds elements t K .. t K + K - 1 in registers: stages
-// at distance j < K stay in the lane, stages at K <= j < 64 K exchange with
-// lane t ^ (j / K) of the same wave (no barrier), and only the stages at
-// 64 K and beyond pass through LDS.  Every thread of the workgroup calls
-// it; it ends with a barrier.
-template <int K>
-__device__ __forceinline__ void bitonic_sort_lanes(const uint64_t* in, uint32_t n, uint64_t* s) {
-    static_assert(K == 4 || K == 8, "keys per lane");
-    const uint32_t T = blockDim.x * (uint32_t)K;
-    const uint32_t t = threadIdx.x, base = t * (uint32_t)K;
-    uint64_t v[K];
-#pragma unroll
-    for (uint32_t r = 0; r < (uint32_t)K; ++r) v[r] = base + r < n ? in[base + r] : ~0ull;
+// Bitonic sort of one key per thread over the workgroup (blockDim.x a power
+// of two, at least 64): returns the key at sorted position threadIdx.x.
+// Stages at distance j < 64 exchange inside the wave (lane_xor), the others
+// through s (blockDim.x words).  Every thread calls it.
+__device__ __forceinline__ uint64_t sort_block_keys(uint64_t v, uint64_t* s) {
+    const uint32_t T = blockDim.x, t = threadIdx.x;
     for (uint32_t k = 2; k <= T; k <<= 1) {
         for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            if (j < (uint32_t)K) {
-                if (j == 1u)
-                    lane_stage<K, 1>(v, base, k);
-                else if (j == 2u)
-                    lane_stage<K, 2>(v, base, k);
-                else
-                    lane_stage<K, (K > 4 ? 4 : 1)>(v, base, k);
-                continue;
-            }
-            // k > j >= K: bit k of every element of the lane is bit k of base
-            const uint32_t m = j / (uint32_t)K;
-            const bool keep_min = ((t & m) == 0u) == ((base & k) == 0u);
-            if (m < 64u) {
-#pragma unroll
-                for (uint32_t r = 0; r < (uint32_t)K; ++r) {
-                    const uint64_t o = lane_xor(v[r], m);
-                    v[r] = ((o < v[r]) == keep_min) ? o : v[r];
-                }
+            const bool keep_min = ((t & j) == 0u) == ((t & k) == 0u);
+            uint64_t o;
+            if (j < 64u) {
+                o = lane_xor(v, j);
             } else {
                 __syncthreads();  // the last exchange's reads are done
-#pragma unroll
-                for (uint32_t r = 0; r < (uint32_t)K; ++r) s[lds_slot(base + r)] = v[r];
+                s[t] = v;
                 __syncthreads();
-                const uint32_t pb = (t ^ m) * (uint32_t)K;
-#pragma unroll
-                for (uint32_t r = 0; r < (uint32_t)K; ++r) {
-                    const uint64_t o = s[lds_slot(pb + r)];
-                    v[r] = ((o < v[r]) == keep_min) ? o : v[r];
-                }
+                o = s[t ^ j];
             }
+            v = ((o < v) == keep_min) ? o : v;
         }
     }
-    __syncthreads();
-#pragma unroll
-    for (uint32_t r = 0; r < (uint32_t)K; ++r) s[lds_slot(base + r)] = v[r];
-    __syncthreads();
+    return v;
 }
-
 
 }  // namespace gccd
