@@ -575,6 +575,7 @@ FieldArgs field_args(const gccd_ctx* c, bool targets_all) {
     fa.ev_off = c->ev_off_d;
     fa.ev_active = c->ev_active_d[c->cur];
     fa.ev_tile = c->ev_tile_d;
+    fa.one_event_n = c->n_events == 1 ? (uint32_t)c->n : 0u;
     fa.targets_all = targets_all ? 1 : 0;
     fa.sources_all = c->p.collected_are_sources;
     fa.px = c->ps[0];
@@ -1915,6 +1916,7 @@ int gccd_field_noalloc(const gccd_params* p, int64_t n, const double* x, const d
     fa.ev_off = ev_off;
     fa.ev_active = ev_active;
     fa.ev_tile = ev_tile;
+    fa.one_event_n = nn;
     fa.targets_all = 1;
     fa.sources_all = p->collected_are_sources;
     fa.px = px;

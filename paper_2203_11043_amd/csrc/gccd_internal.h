@@ -55,6 +55,8 @@ struct FieldArgs {
     const uint32_t* ev_off;     // [E+1] first slot (and carrier) of each event
     const uint32_t* ev_active;  // [E] travelling holes of each event (first in its segment)
     const uint32_t* ev_tile;    // [E+1] first source tile of each event
+    uint32_t one_event_n;       // > 0: a single event of this many carriers (slot 0,
+                                // tile 0), whose offsets the expanded kernel need not read
     int32_t targets_all;        // 1: every carrier of the event is a target
     int32_t sources_all;        // 1: every carrier is a source, else the travelling ones
     const double* px;           // positions in list-slot order (gathered)

@@ -790,19 +790,22 @@ __device__ __forceinline__ double unit_bound(const FieldArgs& a, uint32_t tile0,
 // work items of fewer sources each; the LDS layout is the same.
 template <bool COMP, int UNIT>
 __device__ __forceinline__ void expanded_item(const FieldArgs& a, const FieldItem it,
-                                              ExpandedLds& L) {
+                                              ExpandedLds& L, uint32_t na0) {
     auto& sh = L.sh;
     auto& box = L.box;
     auto& tbox = L.tbox;
-    const uint32_t off = a.ev_off[it.event];
-    const uint32_t ne = a.ev_off[it.event + 1] - off;
-    const uint32_t na = a.ev_active[it.event];
+    // a single event (na0: its travelling holes, read with the item) needs
+    // no lookups before the targets' loads
+    const bool one = a.one_event_n != 0u;
+    const uint32_t off = one ? 0u : a.ev_off[it.event];
+    const uint32_t ne = one ? a.one_event_n : a.ev_off[it.event + 1] - off;
+    const uint32_t na = one ? na0 : a.ev_active[it.event];
     const uint32_t nt = a.targets_all ? ne : na;
     const uint32_t ns = a.sources_all ? ne : na;
     const uint32_t tbase = it.blk * (uint32_t)kFieldThreads;
     if (tbase >= nt) return;  // the whole workgroup leaves before any barrier
     const uint32_t ntiles = (ns + UNIT - 1) / UNIT;
-    const uint32_t tile0 = a.ev_tile[it.event];
+    const uint32_t tile0 = one ? 0u : a.ev_tile[it.event];
     const uint32_t chunk = it.group;  // partial-sum group written
     const uint32_t step_t = it.step;
     const uint32_t t_first = it.first;
@@ -984,10 +987,14 @@ __device__ __forceinline__ void expanded_item(const FieldArgs& a, const FieldIte
 // One workgroup per work item.
 template <bool COMP, int UNIT>
 __global__ __launch_bounds__(kFieldThreads) void field_tiles_expanded(FieldArgs a) {
+    // the item, the count and event 0's travelling holes are read together
+    // (the grid never exceeds the item capacity, so the item is in bounds)
+    const FieldItem it = a.items[blockIdx.x];
+    const uint32_t na0 = a.ev_active[0];
     if (a.count_items && blockIdx.x >= *a.n_items) return;  // the whole workgroup
     __shared__ __align__(16) ExpandedLds L;
     if (threadIdx.x == 0) L.xl.n = 0;  // ordered before any push by the item's first barrier
-    expanded_item<COMP, UNIT>(a, a.items[blockIdx.x], L);
+    expanded_item<COMP, UNIT>(a, it, L, na0);
 }
 
 // Persistent form: a fixed grid of workgroups takes the items in list order
@@ -1001,6 +1008,7 @@ void field_queue_expanded(FieldArgs a) {
     __shared__ __align__(16) ExpandedLds L;
     __shared__ uint32_t next;
     const uint32_t n_items = *a.n_items;
+    const uint32_t na0 = a.ev_active[0];
     if (threadIdx.x == 0) L.xl.n = 0;  // ordered before any push by the barriers below
     for (;;) {
         if (threadIdx.x == 0) next = atomicAdd(a.queue, 1u);
@@ -1008,7 +1016,7 @@ void field_queue_expanded(FieldArgs a) {
         const uint32_t i = next;
         __syncthreads();  // every lane has read `next` before lane 0 writes it again
         if (i >= n_items) break;
-        expanded_item<COMP, UNIT>(a, a.items[i], L);
+        expanded_item<COMP, UNIT>(a, a.items[i], L, na0);
     }
 }
 
@@ -1748,7 +1756,8 @@ __device__ __forceinline__ void build_small_list(const StepArgs& a) {
         merge_sorted_runs<kFusedList / kSortItems>(a.keys_out, n, s, kStepThreads);
     for (uint32_t i = threadIdx.x; i < n; i += kStepThreads) a.keys_sorted[i] = s[lds_slot(i)];
     for (uint32_t e = threadIdx.x; e < a.n_events; e += kStepThreads) {
-        const uint32_t off = a.ev_off[e], ne = a.ev_off[e + 1] - off;
+        const uint32_t off = a.one_event ? 0u : a.ev_off[e];
+        const uint32_t ne = a.one_event ? n : a.ev_off[e + 1] - off;
         uint32_t lo = 0, hi = ne;  // first collected key of the segment in [lo, hi]
         while (lo < hi) {
             const uint32_t mid = (lo + hi) >> 1;
@@ -1773,10 +1782,12 @@ __device__ __forceinline__ void build_small_list(const StepArgs& a) {
             src[b] = false;
             const uint32_t g = g0 + b;
             if (g < a.n_tiles) {
-                const uint32_t e = a.tile_event[g];
-                const uint32_t off = a.ev_off[e], ne = a.ev_off[e + 1] - off;
+                // a single event's tiles start at slot 0 (no lookups)
+                const uint32_t e = a.one_event ? 0u : a.tile_event[g];
+                const uint32_t off = a.one_event ? 0u : a.ev_off[e];
+                const uint32_t ne = a.one_event ? n : a.ev_off[e + 1] - off;
                 const uint32_t ns = a.sources_all ? ne : act[e];
-                const uint32_t i = (g - a.ev_tile[e]) * kTile + wave * 64u + lane;
+                const uint32_t i = (a.one_event ? g : g - a.ev_tile[e]) * kTile + wave * 64u + lane;
                 if (i < ne) {
                     const uint32_t c = off + min(key_local(s[lds_slot(off + i)], a.kl), ne - 1u);
                     vx[b] = a.x[c];
