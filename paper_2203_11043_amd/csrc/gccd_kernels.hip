@@ -1734,20 +1734,15 @@ __device__ __forceinline__ double unit_open(uint32_t w) {
 // source tiles, rebuilt by the last workgroup of its step: the new keys,
 // which each workgroup of the step left as a sorted run of its slots
 // (sort_block_keys), merged in LDS (merge_sorted_runs), each event's
-// travelling holes (its
-// first collected key, by binary search in LDS), and the positions and
-// boxes of every source tile in slot order -- the same list, counts, slots
-// and boxes as sort_keys, count_active and gather_tiles.  Wave w gathers
-// quarter w of every tile, four tiles at a time with all their loads in
-// flight together; the tile boxes are reduced from the quarters' in LDS.
-__device__ __forceinline__ double xor_f64(double v, uint32_t m) {
-    return __builtin_bit_cast(double, lane_xor(__builtin_bit_cast(uint64_t, v), m));
-}
-
+// travelling holes (its first collected key, by binary search in LDS), and
+// the positions and boxes of every source tile in slot order -- the same
+// list, counts, slots and boxes as sort_keys, count_active and
+// gather_tiles.  The positions are gathered four slots per thread with all
+// their loads in flight and kept in LDS; the boxes are then reduced by one
+// thread per 16-slot group, per 64-slot quarter and per tile.
 __device__ __forceinline__ void build_small_list(const StepArgs& a) {
     __shared__ uint64_t s[kFusedList + kFusedList / kSortItems];
     __shared__ uint32_t act[kFusedList];
-    __shared__ double qbox[kFusedTiles][4][6];
     const uint32_t n = a.n_all;
     // the step's workgroups left sorted runs of kStepThreads keys
     if (n <= (uint32_t)kFusedList / 2)
@@ -1770,87 +1765,105 @@ __device__ __forceinline__ void build_small_list(const StepArgs& a) {
         a.ev_active_out[e] = lo;
     }
     __syncthreads();
-    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
-    const size_t st = a.box_stride;
+    // positions of every tile slot (tile g, slot w at g kTile + w), gathered
+    // four per thread with all loads in flight, kept in LDS with a flag for
+    // the slots that are sources
+    __shared__ double gp[3][kFusedTiles * kTile];
+    __shared__ uint8_t gsrc[kFusedTiles * kTile];
+    __shared__ double gbox[kFusedTiles * (kTile / 16)][6];
+    const uint32_t nq = a.n_tiles * (uint32_t)kTile;
     constexpr uint32_t kBatch = 4;
-    for (uint32_t g0 = 0; g0 < a.n_tiles; g0 += kBatch) {
-        double vx[kBatch], vy[kBatch], vz[kBatch];
-        bool src[kBatch];
+    for (uint32_t q0 = threadIdx.x; q0 < nq; q0 += kBatch * kStepThreads) {
+        double v[kBatch][3];
+        bool src[kBatch], in[kBatch];
+        uint32_t dst[kBatch];
 #pragma unroll
         for (uint32_t b = 0; b < kBatch; ++b) {
-            vx[b] = vy[b] = vz[b] = 0.0;
-            src[b] = false;
-            const uint32_t g = g0 + b;
-            if (g < a.n_tiles) {
+            const uint32_t q = q0 + b * kStepThreads;
+            v[b][0] = v[b][1] = v[b][2] = 0.0;
+            src[b] = in[b] = false;
+            dst[b] = 0;
+            if (q < nq) {
+                const uint32_t g = q / kTile, w = q % kTile;
                 // a single event's tiles start at slot 0 (no lookups)
                 const uint32_t e = a.one_event ? 0u : a.tile_event[g];
                 const uint32_t off = a.one_event ? 0u : a.ev_off[e];
                 const uint32_t ne = a.one_event ? n : a.ev_off[e + 1] - off;
                 const uint32_t ns = a.sources_all ? ne : act[e];
-                const uint32_t i = (a.one_event ? g : g - a.ev_tile[e]) * kTile + wave * 64u + lane;
+                const uint32_t i = (a.one_event ? g : g - a.ev_tile[e]) * kTile + w;
                 if (i < ne) {
                     const uint32_t c = off + min(key_local(s[lds_slot(off + i)], a.kl), ne - 1u);
-                    vx[b] = a.x[c];
-                    vy[b] = a.y[c];
-                    vz[b] = a.z[c];
-                    a.px[off + i] = vx[b];
-                    a.py[off + i] = vy[b];
-                    a.pz[off + i] = vz[b];
+                    v[b][0] = a.x[c];
+                    v[b][1] = a.y[c];
+                    v[b][2] = a.z[c];
+                    in[b] = true;
                     src[b] = i < ns;
+                    dst[b] = off + i;
                 }
             }
         }
 #pragma unroll
         for (uint32_t b = 0; b < kBatch; ++b) {
-            const uint32_t g = g0 + b;
-            if (g >= a.n_tiles) break;  // uniform
-            double lx = INFINITY, ly = INFINITY, lz = INFINITY;
-            double hx = -INFINITY, hy = -INFINITY, hz = -INFINITY;
-            if (src[b]) {
-                lx = hx = vx[b];
-                ly = hy = vy[b];
-                lz = hz = vz[b];
+            const uint32_t q = q0 + b * kStepThreads;
+            if (q >= nq) break;
+            if (in[b]) {
+                a.px[dst[b]] = v[b][0];
+                a.py[dst[b]] = v[b][1];
+                a.pz[dst[b]] = v[b][2];
             }
-#pragma unroll
-            for (int m = 1; m <= 8; m <<= 1) {
-                lx = fmin(lx, xor_f64(lx, m));
-                ly = fmin(ly, xor_f64(ly, m));
-                lz = fmin(lz, xor_f64(lz, m));
-                hx = fmax(hx, xor_f64(hx, m));
-                hy = fmax(hy, xor_f64(hy, m));
-                hz = fmax(hz, xor_f64(hz, m));
-            }
-            if ((lane & 15u) == 0) {
-                const uint32_t grp = wave * 4u + (lane >> 4);  // 16-slot group of the tile
-                const double v[6] = {lx, ly, lz, hx, hy, hz};
-#pragma unroll
-                for (int k = 0; k < 6; ++k) a.tile_box[(size_t)(30 + 16 * k + grp) * st + g] = v[k];
-            }
-#pragma unroll
-            for (int m = 16; m <= 32; m <<= 1) {
-                lx = fmin(lx, xor_f64(lx, m));
-                ly = fmin(ly, xor_f64(ly, m));
-                lz = fmin(lz, xor_f64(lz, m));
-                hx = fmax(hx, xor_f64(hx, m));
-                hy = fmax(hy, xor_f64(hy, m));
-                hz = fmax(hz, xor_f64(hz, m));
-            }
-            if (lane == 0) {
-                const double v[6] = {lx, ly, lz, hx, hy, hz};
-#pragma unroll
-                for (int k = 0; k < 6; ++k) {
-                    a.tile_box[(size_t)(6 + 4 * k + wave) * st + g] = v[k];
-                    qbox[g][wave][k] = v[k];
-                }
-            }
+            gp[0][q] = v[b][0];
+            gp[1][q] = v[b][1];
+            gp[2][q] = v[b][2];
+            gsrc[q] = src[b] ? 1 : 0;
         }
     }
     __syncthreads();
-    for (uint32_t q = threadIdx.x; q < 6u * a.n_tiles; q += kStepThreads) {
-        const uint32_t g = q / 6u, k = q % 6u;
-        double v = qbox[g][0][k];
-        for (int w = 1; w < 4; ++w) v = (k < 3) ? fmin(v, qbox[g][w][k]) : fmax(v, qbox[g][w][k]);
-        a.tile_box[(size_t)k * st + g] = v;
+    // the boxes of the sources: one thread per 16-slot group, then one per
+    // 64-slot quarter (four groups), then one per tile (four quarters)
+    const size_t st = a.box_stride;
+    const uint32_t ng = a.n_tiles * (uint32_t)(kTile / 16);
+    for (uint32_t t = threadIdx.x; t < ng; t += kStepThreads) {
+        double b[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+#pragma unroll 4
+        for (uint32_t w = t * 16u; w < t * 16u + 16u; ++w) {
+            if (!gsrc[w]) continue;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                b[k] = fmin(b[k], gp[k][w]);
+                b[3 + k] = fmax(b[3 + k], gp[k][w]);
+            }
+        }
+        const uint32_t g = t / (kTile / 16), grp = t % (kTile / 16);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            gbox[t][k] = b[k];
+            a.tile_box[(size_t)(30 + 16 * k + grp) * st + g] = b[k];
+        }
+    }
+    __syncthreads();
+    __shared__ double qbox[kFusedTiles * 4][6];
+    for (uint32_t t = threadIdx.x; t < a.n_tiles * 4u; t += kStepThreads) {
+        const uint32_t g = t / 4u, qw = t % 4u;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            double m = gbox[t * 4u][k];
+#pragma unroll
+            for (uint32_t j = 1; j < 4; ++j)
+                m = k < 3 ? fmin(m, gbox[t * 4u + j][k]) : fmax(m, gbox[t * 4u + j][k]);
+            qbox[t][k] = m;
+            a.tile_box[(size_t)(6 + 4 * k + qw) * st + g] = m;
+        }
+    }
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < a.n_tiles; t += kStepThreads) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            double m = qbox[t * 4u][k];
+#pragma unroll
+            for (uint32_t j = 1; j < 4; ++j)
+                m = k < 3 ? fmin(m, qbox[t * 4u + j][k]) : fmax(m, qbox[t * 4u + j][k]);
+            a.tile_box[(size_t)k * st + t] = m;
+        }
     }
 }
 
@@ -2113,9 +2126,10 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
         // others
         {
             __shared__ uint64_t sk[kStepThreads];
-            const uint64_t sorted = sort_block_keys(run_key, sk);
-            const uint32_t pos = blockIdx.x * kStepThreads + threadIdx.x;
-            if (pos < a.n_all) a.keys_out[pos] = sorted;
+            const uint32_t first = blockIdx.x * kStepThreads;
+            const uint32_t m = min((uint32_t)kStepThreads, a.n_all - first);
+            const uint64_t sorted = sort_block_keys(run_key, m, sk);
+            if (threadIdx.x < m) a.keys_out[first + threadIdx.x] = sorted;
         }
         // the last workgroup to arrive rebuilds the list: each thread's
         // stores of the step are made visible at device scope before its

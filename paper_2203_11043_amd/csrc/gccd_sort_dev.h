@@ -140,28 +140,28 @@ __device__ __forceinline__ uint64_t lane_xor(uint64_t v, uint32_t m) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Bitonic sort of one key per thread over the workgroup (blockDim.x a power
-// of two, at least 64): returns the key at sorted position threadIdx.x.
-// Stages at distance j < 64 exchange inside the wave (lane_xor), the others
-// through s (blockDim.x words).  Every thread calls it.
-__device__ __forceinline__ uint64_t sort_block_keys(uint64_t v, uint64_t* s) {
-    const uint32_t T = blockDim.x, t = threadIdx.x;
-    for (uint32_t k = 2; k <= T; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            const bool keep_min = ((t & j) == 0u) == ((t & k) == 0u);
-            uint64_t o;
-            if (j < 64u) {
-                o = lane_xor(v, j);
-            } else {
-                __syncthreads();  // the last exchange's reads are done
-                s[t] = v;
-                __syncthreads();
-                o = s[t ^ j];
-            }
-            v = ((o < v) == keep_min) ? o : v;
-        }
+// Sort of one key per thread over the workgroup by rank: thread t < m holds
+// one of m distinct keys and counts the keys below its own (m broadcast LDS
+// reads, two VALU each, no dependent chain), then writes it at that rank;
+// threads from m on (no key) keep their places after every key.  Returns
+// the key at sorted position threadIdx.x (~0 from m on).  For a few hundred
+// keys this is several times faster than a bitonic network, whose stages
+// each wait on a lane exchange.  s holds blockDim.x words; every thread
+// calls it.
+__device__ __forceinline__ uint64_t sort_block_keys(uint64_t v, uint32_t m, uint64_t* s) {
+    const uint32_t t = threadIdx.x;
+    if (t >= m) v = ~0ull;
+    s[t] = v;
+    __syncthreads();
+    uint32_t r = t;
+    if (t < m) {
+        r = 0;
+        for (uint32_t u = 0; u < m; ++u) r += s[u] < v ? 1u : 0u;
     }
-    return v;
+    __syncthreads();
+    s[r] = v;
+    __syncthreads();
+    return s[t];
 }
 
 }  // namespace gccd
