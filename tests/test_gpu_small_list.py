@@ -1,7 +1,8 @@
 """Loads of at most 2048 holes rebuild the sorted carrier list inside the
-step kernel: its last workgroup sorts the new keys in LDS, finds each
-event's travelling holes and gathers the positions and boxes of the source
-tiles, where larger loads launch the sort, the count and the gather
+step kernel: each workgroup sorts its 256 slots' new keys into a run, and
+the last one merges the runs in LDS (1024- and 2048-key merges below), finds
+each event's travelling holes and gathers the positions and boxes of the
+source tiles, where larger loads launch the sort, the count and the gather
 separately.  The keys are unique, so both must give the same list.
 
 After runs that collect part of the holes, the list the step kernel left is
@@ -73,7 +74,7 @@ def run_then_compare(g, d, x, y, z, offsets=None, steps=None, until_active=None)
     return E1, E2, done, int(np.sum(cs < 0))
 
 
-@pytest.mark.parametrize("n,sources", [(2000, 1), (2048, 1), (1500, 0), (1, 1)])
+@pytest.mark.parametrize("n,sources", [(2000, 1), (2048, 1), (1500, 0), (700, 1), (1, 1)])
 def test_single_cloud_list(g, W, n, sources):
     x, y, z = W.gaussian_cloud(n, W.cloud_sigma(n), (480.0, 480.0, 20.0), 91, stream=n)
     d = dict(W.DEVICE, collected_are_sources=sources)
