@@ -131,15 +131,6 @@ __device__ __forceinline__ void merge_sorted_runs(const uint64_t* in, uint32_t c
     merge_levels<THREADS>(v, s, w0);
 }
 
-// 64-bit value of lane (this lane ^ m) of the wave: two LDS-crossbar
-// permutes with the byte index computed once.
-__device__ __forceinline__ uint64_t lane_xor(uint64_t v, uint32_t m) {
-    const int idx = (int)((__lane_id() ^ m) << 2);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(idx, (int)(uint32_t)v);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(idx, (int)(uint32_t)(v >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
-
 // Sort of one key per thread over the workgroup by rank: thread t < m holds
 // one of m distinct keys and counts the keys below its own (m broadcast LDS
 // reads, two VALU each, no dependent chain), then writes it at that rank;
