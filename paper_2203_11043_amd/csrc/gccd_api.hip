@@ -632,11 +632,12 @@ int gather(gccd_ctx* c) {
     return GCCD_OK;
 }
 
-// The sorted list from the keys in `unsorted` (clobbered): sort into
-// keys[cur], count each event's travelling holes, gather the positions.
-int finish_list(gccd_ctx* c, uint64_t* unsorted) {
+// The sorted list from the keys in `unsorted` (clobbered; with run0 > 0 it
+// holds sorted runs of run0 keys): sort into keys[cur], count each event's
+// travelling holes, gather the positions.
+int finish_list(gccd_ctx* c, uint64_t* unsorted, uint32_t run0 = 0) {
     const uint32_t n = (uint32_t)c->n;
-    GCCD_HIP(c, sort_keys(unsorted, c->keys[c->cur], n, c->stream));
+    GCCD_HIP(c, sort_keys(unsorted, c->keys[c->cur], n, c->stream, run0));
     GCCD_HIP(c, launch_count(c->keys[c->cur], c->ev_off_d, c->n_events, c->kl,
                              c->ev_active_d[c->cur], c->stream));
     return gather(c);
@@ -1534,6 +1535,10 @@ int gccd_run(gccd_ctx* c, double dt_ps, int64_t max_steps, int64_t* steps_done,
             if (evp) GCCD_HIP(c, hipEventRecord(evp[1], c->stream));
             sa.keys_in = c->keys[c->cur];
             sa.keys_out = c->ukeys[c->u];
+            // a serial list: the step kernel's workgroups sort their slots'
+            // keys into runs, so the sort only merges them (the side stream's
+            // sort of a pipelined list overlaps the field and gains nothing)
+            sa.sort_runs = (!fused && !pipelined) ? 1 : 0;
             sa.ev_active = c->ev_active_d[c->cur];
             if (fused) {  // the kernel leaves the next step's list in place of this one's
                 sa.keys_sorted = c->keys[c->cur];
@@ -1541,7 +1546,8 @@ int gccd_run(gccd_ctx* c, double dt_ps, int64_t max_steps, int64_t* steps_done,
             }
             GCCD_HIP(c, launch_step(sa, n, c->stream));
             if (fused) return GCCD_OK;
-            if (!pipelined) return finish_list(c, c->ukeys[c->u]);  // the next step's list
+            if (!pipelined)  // the next step's list, from the runs the step kernel sorted
+                return finish_list(c, c->ukeys[c->u], kStepThreads);
             // The list of the new positions is sorted on the side stream while
             // the next step runs over the one the side stream finished last
             // (the first step of a stretch follows the join of the last one).

@@ -105,6 +105,9 @@ struct StepArgs {
     const uint64_t* keys_in;   // the list this step runs over (list mode; its segments
                                // may be one step old: a hole travels while cstep < 0)
     uint64_t* keys_out;        // every slot's new key, before sorting (list mode)
+    int32_t sort_runs;         // list mode: keys_out as sorted runs of kStepThreads slots
+                               // (each workgroup turn sorts its own), for a sort that
+                               // then only merges them
     const uint32_t* ev_off;    // [E+1]
     const uint32_t* ev_active; // [E] travelling holes of each event in keys_in (list mode)
     int32_t sources_all;       // sources of a target's Eq. (6) sum: its whole event, or
@@ -260,6 +263,9 @@ hipError_t launch_far(const float* F, const GridParams* gp, const double* px, co
 
 // Sorts the n keys of `keys` into `out` (merge sort, gccd_sort.hip); `keys`
 // is used as the other buffer of the merge levels and left in no useful order.
-hipError_t sort_keys(uint64_t* keys, uint64_t* out, uint32_t n, hipStream_t s);
+// run0 > 0: keys[0, n) already consists of sorted runs of run0 keys (a power
+// of two from kSortItems to the block-sort tile), which are only merged.
+hipError_t sort_keys(uint64_t* keys, uint64_t* out, uint32_t n, hipStream_t s,
+                     uint32_t run0 = 0);
 
 }  // namespace gccd

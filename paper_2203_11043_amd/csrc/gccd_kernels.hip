@@ -1910,10 +1910,15 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
     const int lane = threadIdx.x & 63;
     uint32_t kept = 0;  // this wave's holes still travelling (wave-uniform)
     unsigned long long pairs = 0;  // this lane's pair interactions of Eq. (6)
-    uint64_t run_key = ~0ull;      // FUSE: this slot's new key (one slot per thread)
+    // FUSE, or a.sort_runs: each turn's kStepThreads slots leave their new
+    // keys as one sorted run (sort_block_keys), which the next sort only
+    // merges; else every slot leaves its key in place
+    const bool runs = FUSE || (LIST && a.sort_runs != 0);
+    __shared__ uint64_t sk[kStepThreads];
     for (uint32_t base = blockIdx.x * kStepThreads; base < a.n_all;
          base += gridDim.x * kStepThreads) {
         const uint32_t slot = base + threadIdx.x;
+        uint64_t run_key = ~0ull;  // this slot's new key, when the keys form runs
         bool keep = false;
         if (slot < a.n_all) {
             uint32_t e, j, local, src = 0u;
@@ -2092,12 +2097,17 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
                 keep = !collected;
                 if (LIST) key = make_key(e, collected, xn, yn, zn, local, a.kl);
             }
-            if constexpr (FUSE)
+            if (runs)
                 run_key = key;
             else if (LIST)
                 a.keys_out[slot] = key;
         }
         kept += (uint32_t)__popcll(__ballot(keep));
+        if (runs) {  // uniform: every thread of the workgroup takes each turn
+            const uint32_t m = min((uint32_t)kStepThreads, a.n_all - base);
+            const uint64_t sorted = sort_block_keys(run_key, m, sk);
+            if (threadIdx.x < m) a.keys_out[base + threadIdx.x] = sorted;
+        }
     }
     // one atomic per workgroup for each count: a counter taking one per wave
     // and grid-stride turn (2.6e5 at 2^24 holes) serialised the whole step
@@ -2121,17 +2131,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a) {
         if (pr && a.coulomb) atomicAdd(&a.stats[1], pr);
     }
     if constexpr (FUSE) {
-        // the workgroup's slots (one per thread) leave their new keys as a
-        // sorted run of kStepThreads, which the list rebuild merges with the
-        // others
-        {
-            __shared__ uint64_t sk[kStepThreads];
-            const uint32_t first = blockIdx.x * kStepThreads;
-            const uint32_t m = min((uint32_t)kStepThreads, a.n_all - first);
-            const uint64_t sorted = sort_block_keys(run_key, m, sk);
-            if (threadIdx.x < m) a.keys_out[first + threadIdx.x] = sorted;
-        }
-        // the last workgroup to arrive rebuilds the list: each thread's
+        // the last workgroup to arrive rebuilds the list (merging the runs
+        // the workgroups left): each thread's
         // stores of the step are made visible at device scope before its
         // workgroup arrives, and the last one sees every workgroup's
         __shared__ uint32_t last;

@@ -22,15 +22,20 @@ constexpr int kSortThreads = 512;
 constexpr uint32_t kSortTile = kSortThreads * kSortItems;  // 4096
 
 // One tile of T = THREADS * kSortItems keys per workgroup, sorted in LDS
-// (block_sort_lds); loads and stores of global memory are coalesced.
+// (block_sort_lds; with run0 > 0 the tile's runs of run0 keys are already
+// sorted and only merged, merge_sorted_runs); loads and stores of global
+// memory are coalesced.
 template <int THREADS>
 __global__ __launch_bounds__(THREADS) void block_sort(const uint64_t* in, uint64_t* out,
-                                                      uint32_t n) {
+                                                      uint32_t n, uint32_t run0) {
     constexpr uint32_t T = (uint32_t)THREADS * kSortItems;
     __shared__ uint64_t s[T + T / kSortItems];
     const uint32_t b0 = blockIdx.x * T;
     const uint32_t cnt = min(T, n - b0);
-    block_sort_lds<THREADS>(in + b0, cnt, s);
+    if (run0 != 0u)
+        merge_sorted_runs<THREADS>(in + b0, cnt, s, min(run0, T));
+    else
+        block_sort_lds<THREADS>(in + b0, cnt, s);
     for (uint32_t i = threadIdx.x; i < cnt; i += THREADS) out[b0 + i] = s[lds_slot(i)];
 }
 
@@ -134,23 +139,25 @@ __global__ __launch_bounds__(kSortThreads) void merge_runs(const uint64_t* in, u
 }
 
 // Sorts keys[0, n) (clobbered) into out[0, n).
-hipError_t sort_keys(uint64_t* keys, uint64_t* out, uint32_t n, hipStream_t s) {
+hipError_t sort_keys(uint64_t* keys, uint64_t* out, uint32_t n, hipStream_t s, uint32_t run0) {
     if (n == 0) return hipSuccess;
+    if (run0 != 0u && (run0 < (uint32_t)kSortItems || (run0 & (run0 - 1u)) != 0u))
+        return hipErrorInvalidValue;
     const uint32_t tiles = (n + kSortTile - 1) / kSortTile;
     int levels = 0;
     for (uint64_t r = kSortTile; r < n; r <<= 1) ++levels;
     // the block sort writes where `levels` merges, alternating, end in out
     uint64_t* src = (levels & 1) ? keys : out;
     if (n <= 32u * kSortItems)
-        block_sort<32><<<1, 32, 0, s>>>(keys, src, n);
+        block_sort<32><<<1, 32, 0, s>>>(keys, src, n, run0);
     else if (n <= 64u * kSortItems)
-        block_sort<64><<<1, 64, 0, s>>>(keys, src, n);
+        block_sort<64><<<1, 64, 0, s>>>(keys, src, n, run0);
     else if (n <= 128u * kSortItems)
-        block_sort<128><<<1, 128, 0, s>>>(keys, src, n);
+        block_sort<128><<<1, 128, 0, s>>>(keys, src, n, run0);
     else if (n <= 256u * kSortItems)
-        block_sort<256><<<1, 256, 0, s>>>(keys, src, n);
+        block_sort<256><<<1, 256, 0, s>>>(keys, src, n, run0);
     else
-        block_sort<kSortThreads><<<tiles, kSortThreads, 0, s>>>(keys, src, n);
+        block_sort<kSortThreads><<<tiles, kSortThreads, 0, s>>>(keys, src, n, run0);
     hipError_t e = hipGetLastError();
     uint64_t w = kSortTile;
     for (int l = 0; l < levels && e == hipSuccess; ++l, w <<= 1) {
