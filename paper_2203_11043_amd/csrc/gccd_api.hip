@@ -638,6 +638,14 @@ int gather(gccd_ctx* c) {
 int finish_list(gccd_ctx* c, uint64_t* unsorted, uint32_t run0 = 0) {
     const uint32_t n = (uint32_t)c->n;
     GCCD_HIP(c, sort_keys(unsorted, c->keys[c->cur], n, c->stream, run0));
+    if (c->p.collected_are_sources) {  // the gather needs no count: one launch
+        GCCD_HIP(c, launch_gather_count(c->keys[c->cur], c->ev_off_d, c->ev_tile_d,
+                                        c->tile_event_d, c->n_events, c->n_tiles, c->kl, c->x,
+                                        c->y, c->z, c->ps[0], c->ps[1], c->ps[2], c->tile_box,
+                                        std::max<uint32_t>(c->n_tiles, 1),
+                                        c->ev_active_d[c->cur], c->stream));
+        return GCCD_OK;
+    }
     GCCD_HIP(c, launch_count(c->keys[c->cur], c->ev_off_d, c->n_events, c->kl,
                              c->ev_active_d[c->cur], c->stream));
     return gather(c);

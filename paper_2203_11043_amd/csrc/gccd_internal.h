@@ -177,6 +177,13 @@ hipError_t launch_load(double* z, int32_t* cstep, const uint32_t* ev_off, uint32
 hipError_t launch_make_keys(const double* x, const double* y, const double* z,
                             const int32_t* cstep, const uint32_t* ev_of, const uint32_t* ev_off,
                             uint32_t n, KeyLayout kl, uint64_t* keys, hipStream_t s);
+// launch_gather and launch_count in one launch (every hole a source).
+hipError_t launch_gather_count(const uint64_t* keys, const uint32_t* ev_off,
+                               const uint32_t* ev_tile, const uint32_t* tile_event,
+                               uint32_t n_events, uint32_t n_tiles, KeyLayout kl, const double* x,
+                               const double* y, const double* z, double* px, double* py,
+                               double* pz, double* box, uint32_t stride, uint32_t* ev_active,
+                               hipStream_t s);
 hipError_t launch_gather(const uint64_t* keys, const uint32_t* ev_off, const uint32_t* ev_tile,
                          const uint32_t* tile_event, const uint32_t* ev_active, int sources_all,
                          uint32_t n_tiles, KeyLayout kl, const double* x, const double* y,

@@ -1677,6 +1677,62 @@ __global__ __launch_bounds__(kTile) void gather_tiles(
         stride, red);
 }
 
+// gather_tiles and count_active in one launch, for lists whose sources are
+// every hole (the gather then needs no count): tile g also finds whether the
+// event's first collected key -- its travelling count, the keys of a
+// segment being ordered travelling before collected -- lies in its slots.
+// Exactly one workgroup writes each event's count: the one whose tile holds
+// the first collected key (the slot before the tile travelling, or the tile
+// first in its event), or the event's last tile if no key is collected;
+// workgroup 0 writes 0 for the events with no holes (and no tiles).
+__global__ __launch_bounds__(kTile) void gather_count_tiles(
+    const uint64_t* keys, const uint32_t* ev_off, const uint32_t* ev_tile,
+    const uint32_t* tile_event, uint32_t n_events, KeyLayout kl, const double* x,
+    const double* y, const double* z, double* px, double* py, double* pz, double* box,
+    uint32_t stride, uint32_t* ev_active) {
+    __shared__ double red[6][kTile / 64];
+    __shared__ uint32_t first_col[kTile / 64];
+    const uint32_t g = blockIdx.x;
+    if (g == 0) {
+        for (uint32_t e = threadIdx.x; e < n_events; e += kTile)
+            if (ev_off[e + 1] == ev_off[e]) ev_active[e] = 0u;
+    }
+    gather_tile(
+        g, [&](uint32_t slot) { return keys[slot]; }, ev_off, ev_tile, tile_event, 0u, 1, kl,
+        x, y, z, px, py, pz, box, stride, red);
+    const uint32_t e = tile_event[g];
+    const uint32_t t0 = (g - ev_tile[e]) * kTile;
+    const uint32_t off = ev_off[e], ne = ev_off[e + 1] - off;
+    const uint32_t i = t0 + threadIdx.x;
+    const bool col = i < ne && key_collected(keys[off + i], kl);
+    const uint64_t bal = __ballot(col);
+    const uint32_t wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63u) == 0)
+        first_col[wave] = bal ? wave * 64u + (uint32_t)__builtin_ctzll(bal) : (uint32_t)kTile;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t p = (uint32_t)kTile;  // first collected slot of the tile, from its start
+        for (uint32_t w = 0; w < kTile / 64; ++w) p = min(p, first_col[w]);
+        if (p < (uint32_t)kTile) {
+            if (t0 == 0u || !key_collected(keys[off + t0 - 1u], kl)) ev_active[e] = t0 + p;
+        } else if (t0 + (uint32_t)kTile >= ne) {
+            ev_active[e] = ne;  // the event's last tile, and no key collected
+        }
+    }
+}
+
+hipError_t launch_gather_count(const uint64_t* keys, const uint32_t* ev_off,
+                               const uint32_t* ev_tile, const uint32_t* tile_event,
+                               uint32_t n_events, uint32_t n_tiles, KeyLayout kl, const double* x,
+                               const double* y, const double* z, double* px, double* py,
+                               double* pz, double* box, uint32_t stride, uint32_t* ev_active,
+                               hipStream_t s) {
+    if (n_tiles == 0) return launch_count(keys, ev_off, n_events, kl, ev_active, s);
+    gather_count_tiles<<<n_tiles, kTile, 0, s>>>(keys, ev_off, ev_tile, tile_event, n_events, kl,
+                                                 x, y, z, px, py, pz, box, stride, ev_active);
+    return hipGetLastError();
+}
+
 hipError_t launch_gather(const uint64_t* keys, const uint32_t* ev_off, const uint32_t* ev_tile,
                          const uint32_t* tile_event, const uint32_t* ev_active, int sources_all,
                          uint32_t n_tiles, KeyLayout kl, const double* x, const double* y,
