@@ -283,8 +283,8 @@ int gccd_set_precision(gccd_ctx* c, int32_t mode);
  * Per-launch timing (gccd_set_timing) needs events around each field
  * launch, which graph replays do not provide: with timing on, GRAPH issues
  * its steps one by one.  Default: GRAPH, the fastest measured on MI355X:
- * replays save the launch gaps of the short steps of small loads (0.038
- * against 0.044 ms per step at 1000 holes, 0.055 against 0.063 at 3000)
+ * replays save the launch gaps of the short steps of small loads (0.037
+ * against 0.044 ms per step at 1000 holes, 0.047 against 0.054 at 3000)
  * and are level with GRID at 1e5 holes and at the 4096-cloud batch; the
  * queue costs a reset launch and an atomic per item and is never faster.
  * Synchronises the
