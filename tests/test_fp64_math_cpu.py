@@ -128,3 +128,23 @@ def test_special_values(run):
     assert np.array_equal(ef[fin], e[fin])
     fin = np.isfinite(xp) & (xp > -1.0)
     assert np.array_equal(pf[fin], p[fin])
+
+
+def test_coefficients_are_the_fitted_ones():
+    """The polynomial coefficients in gccd_fp64.h are the ones
+    fp64_coefficients.py fits (40-digit Chebyshev fits rounded to double),
+    each within its printed accuracy."""
+    import re
+    import sys
+    script = os.path.join(INC, "fp64_coefficients.py")
+    out = subprocess.run([sys.executable, script], capture_output=True, text=True,
+                         check=True).stdout
+    fitted = [float(v) for v in re.findall(r"^\s+(-?[0-9.e+-]+),$", out, flags=re.M)]
+    assert len(fitted) == 12 + 7 + 7 + 8
+    header = open(os.path.join(INC, "gccd_fp64.h")).read()
+    for line in out.splitlines():
+        if "max relative error" in line:
+            assert float(line.split()[-1]) < 5e-16, line
+    for v in fitted:
+        if v != 1.0:  # the leading terms, written as 1.0 among others
+            assert repr(v) in header, v
